@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Throughput and latency of the SVT track fitter on one MI355X.
+
+Default workload: 3000 events x 64 roads, 1-3 hits per layer (2048 combinations per event on
+average), the shape of the paper's benchmark sample (section IV).  One step = one pass of the
+whole path (unpack, combine, fit, select) over that batch with the words already in HBM.
+
+Prints one JSON line: the batched path's fitted combinations/s (persistent fused kernel behind
+a replayed HIP graph), the plain one-launch-per-stage path beside it, the roofline of the fused
+kernel (HIP events on its own stream), and the CPU oracle timed on the host as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+METRIC = "fitted combinations/s and p50/p99 event latency (µs), batched vs plain"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(n_combos, n_words, n_roads):
+    """Bytes the fused pass must move: per combination p0..p2 (12) + chi2 (8) + accept (1);
+    per hit word 4 read; per road the best track written (n_accept, k, p0..p2, chi2: 28)."""
+    return 21 * n_combos + 4 * n_words + 28 * n_roads
+
+
+def run_cpu_baseline(sample, bank, cfg, seconds):
+    import oracle
+
+    sec, reps, nc = oracle.time_run(sample.words, bank.f, bank.q, cfg, min_seconds=seconds)
+    return dict(value=nc / sec, unit="fitted combinations/s", cores=1, kind="oracle",
+                sample=f"whole batch ({nc} combinations), {reps} full oracle runs in "
+                       f"{sec * reps:.1f} s, single thread, all outputs")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--wg", type=int, default=0)
+    ap.add_argument("--occ", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the fitter shards by event range with no exchange; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1312_0917_amd import _lib as L
+    from paper_1312_0917_amd import pipeline as P
+    from paper_1312_0917_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dev_name = torch.cuda.get_device_name(0)
+    K, W = args.steps, args.warmup
+
+    log(f"generating {args.config}")
+    bank = synth.make_bank()
+    sample = synth.make_sample(args.config, bank=bank)
+    cut = synth.config_chi2_cut(args.config)
+    cfg = oracle.make_config(chi2_cut=cut)
+    st, n_roads, n_events, n_combos, _ = oracle.count(sample.words, cfg)
+    assert st == 0
+    n_words = len(sample.words)
+    gcfg = L.make_config(chi2_cut=cut)
+    dbank = P.device_bank(bank.f, bank.q)
+    words = P.words_tensor(sample.words)
+    tune = L.make_tune(args.tile, args.chunk, args.wg, args.occ)
+
+    # ---- batched path: resident buffers, graph replay -------------------------------------
+    runner = P.BatchRunner(gcfg, dbank, n_words, n_roads, n_combos, kept_cap=0, tune=tune,
+                           graph=True, with_c=False)
+    runner.load(words)
+    log("batched warmup")
+    for _ in range(W):
+        runner.run()
+    torch.cuda.synchronize()
+    sz = runner.sizes()
+    assert sz["n_combos"] == n_combos and runner.error()[0] == 0, (sz, runner.error())
+    log(f"batched timed: {K} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        runner.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    batch_s = (t1 - t0) / K
+    value = n_combos / batch_s
+
+    # ---- fused kernel alone: HIP events on the runner's stream around each launch ---------
+    log("fused kernel timing")
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(runner.stream)
+    ev1.record(runner.stream)
+    torch.cuda.synchronize()
+    L.svt_set_fused_timing_events(ev0, ev1)
+    runner.graph = False
+    kms = []
+    for i in range(W + K):
+        runner.run()
+        ev1.synchronize()
+        if i >= W:
+            kms.append(ev0.elapsed_time(ev1))
+    L.svt_set_fused_timing_events(None, None)
+    runner.graph = True
+    k_ms = float(np.mean(kms))
+    alg = algorithmic_bytes(n_combos, n_words, n_roads)
+    achieved = alg / (k_ms * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    kernel="k_fused", kernel_ms=round(k_ms, 5), algorithmic_bytes=alg,
+                    bytes_per_combination=round(alg / n_combos, 3))
+
+    # ---- plain path: one launch per stage, host syncs to size each stage ------------------
+    plain = None
+    if not args.no_plain:
+        log("plain path")
+        pr = P.PlainRunner(gcfg, dbank, with_c=False, want_kept=False)
+        for _ in range(W):
+            pr.run(words)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            pr.run(words)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plain_s = (t1 - t0) / K
+        pr.run(words, timing=True)
+        tm = pr.times
+        plain = dict(value=n_combos / plain_s, ms_per_step=round(plain_s * 1e3, 4),
+                     stages_ms=dict(unpack=round(tm.unpack_ms, 4), combine=round(tm.combine_ms, 4),
+                                    fit=round(tm.fit_ms, 4), select=round(tm.select_ms, 4)),
+                     batched_over_plain=round(plain_s / batch_s, 2))
+        del pr
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"cpu oracle baseline (~{args.cpu_seconds:.0f} s)")
+        cpu = run_cpu_baseline(sample, bank, cfg, args.cpu_seconds)
+
+    t = runner.tune
+    out = dict(
+        metric=METRIC, value=value, unit="fitted combinations/s", n_gpus=1, steps=K, warmup=W,
+        ms_per_step=round(batch_s * 1e3, 5), higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="int32/int64", data="synthetic",
+        config=dict(workload=f"{args.config}: {n_events} events, {n_roads} roads, {n_words} hit "
+                             f"words, {n_combos} combinations "
+                             f"({n_combos / max(n_events, 1):.0f} per event)",
+                    events=n_events, roads=n_roads, words=n_words, combinations=n_combos,
+                    chi2_cut=cut, path="svt_process_batch (graph replay)",
+                    tune=dict(tile_combos=t.tile_combos, chunk_roads=t.chunk_roads,
+                              wg_size=t.wg_size, wgs_per_cu=t.wgs_per_cu),
+                    device=dev_name),
+        roofline=roofline, cpu_baseline=cpu, plain=plain)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

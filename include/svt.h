@@ -1,0 +1,214 @@
+/*
+ * svt.h -- C ABI of the SVT linearized track fitter for AMD Instinct MI355X (gfx950).
+ *
+ * The method (Gianelle et al., IEEE NSS 2013, arXiv:1312.0917):
+ *   section II   : every one-hit-per-layer combination of hits inside a road is fitted; each
+ *                  track parameter is a scalar product of pre-defined constants with the hit
+ *                  coordinates plus an offset, p_i = f_i . x_i + q_i, evaluated with table
+ *                  lookups and integer additions and multiplications, together with the
+ *                  chi-square of the fitted track;
+ *   section II-A : the serial code is three stages -- unpack the input words and fill the
+ *                  data structures, compute all hit combinations of each road, fit each
+ *                  combination -- inside loops over events, roads and combinations.
+ * svt_unpack, svt_combine and svt_fit are those three stages; svt_select applies the
+ * chi-square cut and picks the best track of every road; svt_process_batch runs all four as
+ * one persistent fused pass (optionally replayed from a captured HIP graph).
+ *
+ * Exact definitions where the paper is silent (all arithmetic is integer and exact):
+ *   hit word (uint32, LSB first): coord 13 bits two's complement | layer 3 | road tag 8 |
+ *     event tag 8.  A new event starts where the event tag changes, a new road where either
+ *     tag changes (tags are delimiters, roads and events are numbered in stream order).
+ *   constant set of a road = its road tag.  Hits of a road are grouped by layer, stream order
+ *     kept inside a layer.  Combination k of a road is mixed-radix over the layers with layer 0
+ *     most significant (k = ((((h0*n1 + h1)*n2 + h2)*n3 + h3)*n4 + h4).
+ *   v_j = floor((sum_l f[j][l] * x_l + q[j]) / 2^shift), j = 0..5, computed exactly;
+ *     p = v_0..2 (track parameters), c = v_3..5 (chi-square components),
+ *     chi2 = c0^2 + c1^2 + c2^2 (int64).  A combination is accepted when chi2 <= chi2_cut.
+ *   best track of a road: its accepted combination of smallest chi2, the smallest k among
+ *     equal chi2.  A road with none: k = -1, p = INT32_MIN, chi2 = INT64_MAX, n_accept = 0.
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers to device memory are written d_* or are fields of the svt_roads / svt_fitrec /
+ *     svt_best structs; the caller allocates and owns all of them.  Structs themselves and
+ *     svt_config / svt_tune are read from host memory during the call only.
+ *   - The library allocates no device memory.  Scratch comes from the caller's workspace
+ *     (d_work, work_bytes; size from the matching *_workspace function, 256-byte aligned).
+ *     The only library-owned objects are the HIP graphs cached by svt_process_batch, freed by
+ *     svt_release_graphs().
+ *   - Every call only enqueues work on `stream` and returns; nothing synchronises.
+ *   - The return value reports host-side checks: SVT_OK, SVT_ERR_ARG (null pointer, negative
+ *     size, bad configuration, misaligned output), SVT_ERR_HIP (a launch failed).  On an error
+ *     nothing is enqueued.
+ *   - Errors found in the data are written on the device to the error word *d_err (uint64):
+ *     SVT_NO_ERROR (all ones) or (class << 56) | index, and the smallest such value wins, so
+ *     the reported error is deterministic: layer-field errors first (index = word), then too
+ *     many hits in a layer (index = road), then a road tag without a constant set (index =
+ *     road), then capacity (index 0 roads, 1 combinations, 2 kept list).  svt_error_decode()
+ *     turns the word into an svt_status and index.  After a data error the outputs are
+ *     unspecified except the sizes (*d_n_roads, *d_n_combos, *d_n_kept), which are always the
+ *     sizes the input needs, so a caller can grow its buffers and retry.
+ *   - Kernels never write past a capacity and never read outside the given arrays, whatever
+ *     the input words contain.
+ *   - Output arrays of the fused pass must be 16-byte aligned (accept: 4-byte aligned).
+ */
+#ifndef SVT_H
+#define SVT_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SVT_ABI_VERSION 1
+
+typedef int32_t svt_status;
+#define SVT_OK 0
+#define SVT_ERR_ARG (-1)
+#define SVT_ERR_LAYER (-2)
+#define SVT_ERR_HITS (-3)
+#define SVT_ERR_CAPACITY (-4)
+#define SVT_ERR_HIP (-5)
+#define SVT_ERR_SET (-6)
+
+#define SVT_NO_ERROR UINT64_MAX
+#define SVT_ERRCLASS_LAYER 1u
+#define SVT_ERRCLASS_HITS 2u
+#define SVT_ERRCLASS_SET 3u
+#define SVT_ERRCLASS_CAPACITY 4u
+#define SVT_ERRCLASS_INDEX 5u /* svt_fit / svt_select given an out-of-range road or hit index */
+
+#define SVT_N_LAYERS 5
+#define SVT_MAX_HITS 8
+
+/* One constant set (88 bytes): rows 0-2 track parameters, rows 3-5 chi-square components;
+ * column = layer; q is in the scale of f . x (2^shift per unit of the result). */
+typedef struct svt_fconst {
+    int16_t f[6][5];
+    int16_t pad[2];
+    int32_t q[6];
+} svt_fconst;
+
+typedef struct svt_config {
+    int32_t n_layers; /* must be 5 */
+    int32_t shift;    /* fixed-point shift, 1..30 (10 for the benchmark) */
+    int64_t chi2_cut; /* accept when chi2 <= chi2_cut */
+    int32_t max_hits; /* most hits allowed in one layer of a road, 1..8 */
+    int32_t n_sets;   /* constant sets in the bank, 1..256 */
+} svt_config;
+
+/* Road table, structure of arrays, one entry per road in stream order (device memory). */
+typedef struct svt_roads {
+    int32_t *event;       /* event ordinal */
+    int32_t *set;         /* road tag = constant set */
+    int64_t *hit_begin;   /* index of the road's first word (also its first hit_coord) */
+    uint32_t *nhits;      /* hits per layer, 4 bits per layer, layer l in bits 4l..4l+3 */
+    int64_t *combo_begin; /* index of the road's first combination */
+    int32_t *ncombo;      /* number of combinations = product of the hits per layer */
+} svt_roads;
+
+/* Per-combination fit records, structure of arrays (device memory). c0..c2 may be NULL. */
+typedef struct svt_fitrec {
+    int32_t *p0, *p1, *p2;
+    int64_t *chi2;
+    int32_t *c0, *c1, *c2;
+} svt_fitrec;
+
+/* Best track per road (device memory). */
+typedef struct svt_best {
+    int32_t *n_accept;
+    int32_t *k; /* combination index inside the road, -1 when none */
+    int32_t *p0, *p1, *p2;
+    int64_t *chi2;
+} svt_best;
+
+/* Launch parameters of the persistent fused kernel; zeros pick the built-in defaults. */
+typedef struct svt_tune {
+    int32_t tile_combos;  /* combinations per work tile: multiple of 4096, 4096..65536 */
+    int32_t chunk_roads;  /* roads staged in LDS at once: 16, 32 or 64 */
+    int32_t wg_size;      /* 256 or 512 */
+    int32_t wgs_per_cu;   /* persistent workgroups per compute unit, 1..8 */
+} svt_tune;
+
+/* ---- sizes of the caller-provided scratch ------------------------------------------------ */
+int64_t svt_unpack_workspace(int64_t n_words);
+int64_t svt_combine_workspace(int64_t n_roads);
+int64_t svt_select_workspace(int64_t n_combos);
+int64_t svt_batch_workspace(int64_t word_cap, int64_t road_cap, int64_t combo_cap,
+                            const svt_tune *tune);
+
+/* Stage 1, unpack (section II-A, first function): decode words[0..n_words) and fill the road
+ * table fields event, set, hit_begin, nhits for at most road_cap roads; hit_coord[n_words]
+ * receives the int13 coordinates regrouped by layer inside each road (stream order inside a
+ * layer), so road r's layer-l hits start at hit_begin[r] + (hits of layers < l).  Writes the
+ * number of roads to *d_n_roads.  Resets *d_err, then reports layer, hit-count, road-tag
+ * (tag >= n_sets) and road-capacity errors in it.  words: uint32 device array (any alignment). */
+svt_status svt_unpack(const uint32_t *words, int64_t n_words, const svt_config *cfg,
+                      const svt_roads *roads, int64_t road_cap, int16_t *hit_coord,
+                      int64_t *d_n_roads, uint64_t *d_err, void *d_work, int64_t work_bytes,
+                      hipStream_t stream);
+
+/* Stage 2, combine (section II-A, second function): for roads[0..n_roads) set ncombo (product
+ * of the hits per layer) and combo_begin (exclusive prefix sum), write the total to
+ * *d_n_combos and, when combo_road / combo_hits are non-NULL and the total fits combo_cap,
+ * list every combination: its road and its hit index in each layer (4 bits per layer, layer l
+ * in bits 4l..4l+3).  Reports combination-capacity errors in *d_err (not reset). */
+svt_status svt_combine(const svt_roads *roads, int64_t n_roads, const svt_config *cfg,
+                       int32_t *combo_road, uint32_t *combo_hits, int64_t combo_cap,
+                       int64_t *d_n_combos, uint64_t *d_err, void *d_work, int64_t work_bytes,
+                       hipStream_t stream);
+
+/* Stage 3, fit (section II, the scalar-product equation): one fit per listed combination.
+ * bank[n_sets] device array of svt_fconst; hit_coord[n_hits] from svt_unpack; combo_road /
+ * combo_hits[n_combos] from svt_combine.  Writes out->p0..p2, out->chi2 and, when non-NULL,
+ * out->c0..c2.  Indices outside the road table or the hit array are reported in *d_err (class
+ * INDEX, index = combination) and that combination is skipped. */
+svt_status svt_fit(const svt_fconst *bank, const svt_config *cfg, const svt_roads *roads,
+                   int64_t n_roads, const int16_t *hit_coord, int64_t n_hits,
+                   const int32_t *combo_road, const uint32_t *combo_hits, int64_t n_combos,
+                   const svt_fitrec *out, uint64_t *d_err, hipStream_t stream);
+
+/* Stage 4, select: accept[i] = (rec->chi2[i] <= cut); per road n_accept and best track (see
+ * above); when kept is non-NULL, the ascending indices of accepted combinations (at most
+ * kept_cap written, the count in *d_n_kept). */
+svt_status svt_select(const svt_config *cfg, const svt_roads *roads, int64_t n_roads,
+                      const int32_t *combo_road, const svt_fitrec *rec, int64_t n_combos,
+                      uint8_t *accept, const svt_best *best, int64_t *kept, int64_t kept_cap,
+                      int64_t *d_n_kept, uint64_t *d_err, void *d_work, int64_t work_bytes,
+                      hipStream_t stream);
+
+/* The whole path in one pass: the words are segmented and sized by a short pre-pass, then a
+ * persistent fused kernel takes tiles of tile_combos consecutive combinations, stages the
+ * roads' hits and fit-constant partial sums in LDS, fits every combination with integer VALU
+ * arithmetic and writes the same records, accept flags, road table and best tracks as stages
+ * 1-4 (bit for bit).  The word count is read on the device from *d_n_words, so a captured
+ * graph can be replayed for any batch up to word_cap.  flags: SVT_BATCH_GRAPH captures the
+ * launch sequence in a HIP graph on first use (keyed by every argument) and replays it
+ * afterwards.  kept may be NULL.  Resets *d_err. */
+#define SVT_BATCH_GRAPH 1
+svt_status svt_process_batch(const svt_fconst *bank, const svt_config *cfg, const svt_tune *tune,
+                             const uint32_t *words, const int64_t *d_n_words, int64_t word_cap,
+                             const svt_roads *roads, int64_t road_cap, const svt_fitrec *rec,
+                             uint8_t *accept, int64_t combo_cap, const svt_best *best,
+                             int64_t *kept, int64_t kept_cap, int64_t *d_n_roads,
+                             int64_t *d_n_combos, int64_t *d_n_kept, uint64_t *d_err,
+                             void *d_work, int64_t work_bytes, int32_t flags, hipStream_t stream);
+
+/* When both are non-NULL, svt_process_batch calls without SVT_BATCH_GRAPH record `start`
+ * right before and `stop` right after the fused kernel, on the call's stream (for timing). */
+void svt_set_fused_timing_events(hipEvent_t start, hipEvent_t stop);
+
+/* Destroy every cached graph (call before freeing buffers a cached graph refers to). */
+void svt_release_graphs(void);
+
+/* Turn an error word into a status (SVT_OK when none) and its index (-1 when none). */
+svt_status svt_error_decode(uint64_t err, int64_t *index);
+
+const char *svt_status_name(svt_status s);
+int32_t svt_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SVT_H */

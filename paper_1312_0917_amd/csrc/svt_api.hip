@@ -1,0 +1,430 @@
+// Host side of the libsvt C ABI: argument checks, workspace layout, launch sequences and the
+// HIP-graph cache of svt_process_batch.  Every function only enqueues on the given stream.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "svt_common.h"
+
+using namespace svt;
+
+namespace {
+
+constexpr int64_t kAlign = 256;
+inline int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+bool config_ok(const svt_config *c) {
+    return c && c->n_layers == SVT_N_LAYERS && c->shift >= 1 && c->shift <= 30 &&
+           c->max_hits >= 1 && c->max_hits <= SVT_MAX_HITS && c->n_sets >= 1 && c->n_sets <= 256;
+}
+
+bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Workspace carving: a bump allocator over the caller's buffer.
+struct Carver {
+    char *base;
+    int64_t used = 0;
+    template <typename T>
+    T *take(int64_t count) {
+        T *p = base ? reinterpret_cast<T *>(base + used) : nullptr;
+        used += align_up(static_cast<int64_t>(sizeof(T)) * (count > 0 ? count : 1));
+        return p;
+    }
+};
+
+struct UnpackWs {
+    int64_t *scalars;  // [0] event total
+    int64_t *wb;       // [2][nb]
+    int64_t nb;
+};
+UnpackWs carve_unpack(Carver &c, int64_t n_words) {
+    UnpackWs w;
+    w.nb = ceil_div(n_words > 0 ? n_words : 1, kSegBlockWords);
+    w.scalars = c.take<int64_t>(4);
+    w.wb = c.take<int64_t>(2 * w.nb);
+    return w;
+}
+
+struct BatchWs {
+    int64_t *scalars;  // [0] event total
+    uint32_t *tile_counter;
+    int64_t *wb;
+    int64_t nb;
+    int64_t *rb;
+    int64_t rbn;
+    int32_t *tfr;
+    Partial *part;
+    int64_t tiles_cap;
+    int64_t *kb;
+    int64_t kbn;
+};
+BatchWs carve_batch(Carver &c, int64_t word_cap, int64_t road_cap, int64_t combo_cap,
+                    int64_t tile) {
+    BatchWs w;
+    w.scalars = c.take<int64_t>(4);
+    w.tile_counter = c.take<uint32_t>(4);
+    w.nb = ceil_div(word_cap > 0 ? word_cap : 1, kSegBlockWords);
+    w.wb = c.take<int64_t>(2 * w.nb);
+    w.rbn = ceil_div(road_cap > 0 ? road_cap : 1, kRoadBlock);
+    w.rb = c.take<int64_t>(w.rbn);
+    w.tiles_cap = ceil_div(combo_cap > 0 ? combo_cap : 1, tile) + 1;
+    w.tfr = c.take<int32_t>(w.tiles_cap);
+    w.part = c.take<Partial>(2 * w.tiles_cap);
+    w.kbn = ceil_div(combo_cap > 0 ? combo_cap : 1, kKeptBlock);
+    w.kb = c.take<int64_t>(w.kbn);
+    return w;
+}
+
+svt_tune resolve_tune(const svt_tune *t) {
+    svt_tune r{8192, 64, 256, 4};
+    if (t) {
+        if (t->tile_combos) r.tile_combos = t->tile_combos;
+        if (t->chunk_roads) r.chunk_roads = t->chunk_roads;
+        if (t->wg_size) r.wg_size = t->wg_size;
+        if (t->wgs_per_cu) r.wgs_per_cu = t->wgs_per_cu;
+    }
+    return r;
+}
+
+int num_cus() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    static std::mutex mu;
+    static std::map<int, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) n = 0;
+    cache[dev] = n;
+    return n;
+}
+
+#define SVT_TRY(x)                                  \
+    do {                                            \
+        if ((x) != hipSuccess) return SVT_ERR_HIP;  \
+    } while (0)
+
+hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+std::mutex g_graph_mu;
+
+using GraphKey = std::vector<uint64_t>;
+struct GraphEntry {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+std::map<GraphKey, GraphEntry> &graph_cache() {
+    static std::map<GraphKey, GraphEntry> m;
+    return m;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t svt_abi_version(void) { return SVT_ABI_VERSION; }
+
+const char *svt_status_name(svt_status s) {
+    switch (s) {
+        case SVT_OK: return "SVT_OK";
+        case SVT_ERR_ARG: return "SVT_ERR_ARG";
+        case SVT_ERR_LAYER: return "SVT_ERR_LAYER";
+        case SVT_ERR_HITS: return "SVT_ERR_HITS";
+        case SVT_ERR_CAPACITY: return "SVT_ERR_CAPACITY";
+        case SVT_ERR_HIP: return "SVT_ERR_HIP";
+        case SVT_ERR_SET: return "SVT_ERR_SET";
+        default: return "SVT_ERR_UNKNOWN";
+    }
+}
+
+svt_status svt_error_decode(uint64_t err, int64_t *index) {
+    if (err == SVT_NO_ERROR) {
+        if (index) *index = -1;
+        return SVT_OK;
+    }
+    const uint32_t cls = static_cast<uint32_t>(err >> 56);
+    if (index) *index = static_cast<int64_t>(err & ((1ull << 56) - 1));
+    switch (cls) {
+        case SVT_ERRCLASS_LAYER: return SVT_ERR_LAYER;
+        case SVT_ERRCLASS_HITS: return SVT_ERR_HITS;
+        case SVT_ERRCLASS_SET: return SVT_ERR_SET;
+        case SVT_ERRCLASS_CAPACITY: return SVT_ERR_CAPACITY;
+        default: return SVT_ERR_ARG;
+    }
+}
+
+int64_t svt_unpack_workspace(int64_t n_words) {
+    if (n_words < 0) return -1;
+    Carver c{nullptr};
+    carve_unpack(c, n_words);
+    return c.used;
+}
+
+int64_t svt_combine_workspace(int64_t n_roads) {
+    if (n_roads < 0) return -1;
+    return align_up(8 * ceil_div(n_roads > 0 ? n_roads : 1, kRoadBlock));
+}
+
+int64_t svt_select_workspace(int64_t n_combos) {
+    if (n_combos < 0) return -1;
+    return align_up(8 * ceil_div(n_combos > 0 ? n_combos : 1, kKeptBlock));
+}
+
+int64_t svt_batch_workspace(int64_t word_cap, int64_t road_cap, int64_t combo_cap,
+                            const svt_tune *tune) {
+    if (word_cap < 0 || road_cap < 0 || combo_cap < 0) return -1;
+    const svt_tune t = resolve_tune(tune);
+    if (!fused_tune_supported(t)) return -1;
+    Carver c{nullptr};
+    carve_batch(c, word_cap, road_cap, combo_cap, t.tile_combos);
+    return c.used;
+}
+
+svt_status svt_unpack(const uint32_t *words, int64_t n_words, const svt_config *cfg,
+                      const svt_roads *roads, int64_t road_cap, int16_t *hit_coord,
+                      int64_t *d_n_roads, uint64_t *d_err, void *d_work, int64_t work_bytes,
+                      hipStream_t stream) {
+    if (!config_ok(cfg) || !roads || n_words < 0 || road_cap < 0 || !d_n_roads || !d_err)
+        return SVT_ERR_ARG;
+    if (n_words > 0 && (!words || !hit_coord)) return SVT_ERR_ARG;
+    if (road_cap > 0 && (!roads->event || !roads->set || !roads->hit_begin || !roads->nhits))
+        return SVT_ERR_ARG;
+    if (!d_work || work_bytes < svt_unpack_workspace(n_words) || !aligned(d_work, kAlign))
+        return SVT_ERR_ARG;
+    Carver c{static_cast<char *>(d_work)};
+    UnpackWs w = carve_unpack(c, n_words);
+    const Sizes nw{n_words, nullptr, n_words};
+    SVT_TRY(launch_init_err(d_err, stream));
+    SVT_TRY(launch_seg_count(words, nw, w.nb, cfg->n_layers, w.wb, d_err, stream));
+    SVT_TRY(launch_scan(w.wb, w.nb, 2, nw, kSegBlockWords, d_n_roads, w.scalars, road_cap, 0,
+                        d_err, false, stream));
+    SVT_TRY(launch_seg_emit(words, nw, w.nb, w.wb, *roads, road_cap, d_err, stream));
+    SVT_TRY(launch_road_fill(words, nw, d_n_roads, road_cap, *roads, *cfg, hit_coord, nullptr,
+                             d_err, stream));
+    return SVT_OK;
+}
+
+svt_status svt_combine(const svt_roads *roads, int64_t n_roads, const svt_config *cfg,
+                       int32_t *combo_road, uint32_t *combo_hits, int64_t combo_cap,
+                       int64_t *d_n_combos, uint64_t *d_err, void *d_work, int64_t work_bytes,
+                       hipStream_t stream) {
+    if (!config_ok(cfg) || !roads || n_roads < 0 || combo_cap < 0 || !d_n_combos || !d_err)
+        return SVT_ERR_ARG;
+    if (n_roads > 0 && (!roads->nhits || !roads->ncombo || !roads->combo_begin))
+        return SVT_ERR_ARG;
+    if (!d_work || work_bytes < svt_combine_workspace(n_roads) || !aligned(d_work, kAlign))
+        return SVT_ERR_ARG;
+    int64_t *rb = static_cast<int64_t *>(d_work);
+    const int64_t rbn = ceil_div(n_roads > 0 ? n_roads : 1, kRoadBlock);
+    const Sizes nr{n_roads, nullptr, n_roads};
+    const bool listing = combo_road || combo_hits;
+    SVT_TRY(launch_combo_count(*roads, nr, rbn, rb, d_err, stream));
+    SVT_TRY(launch_scan(rb, 0, 1, nr, kRoadBlock, d_n_combos, nullptr, listing ? combo_cap : -1,
+                        1, d_err, true, stream));
+    SVT_TRY(launch_combo_begin(*roads, nr, rbn, rb, 0, nullptr, 0, nullptr, d_err, stream));
+    if (listing)
+        SVT_TRY(launch_materialize(*roads, n_roads, d_n_combos, combo_cap, combo_road, combo_hits,
+                                   d_err, stream));
+    return SVT_OK;
+}
+
+svt_status svt_fit(const svt_fconst *bank, const svt_config *cfg, const svt_roads *roads,
+                   int64_t n_roads, const int16_t *hit_coord, int64_t n_hits,
+                   const int32_t *combo_road, const uint32_t *combo_hits, int64_t n_combos,
+                   const svt_fitrec *out, uint64_t *d_err, hipStream_t stream) {
+    if (!config_ok(cfg) || !roads || !out || !d_err || n_roads < 0 || n_hits < 0 || n_combos < 0)
+        return SVT_ERR_ARG;
+    if (n_combos > 0 && (!bank || !hit_coord || !combo_road || !combo_hits || !out->p0 ||
+                         !out->p1 || !out->p2 || !out->chi2 || !roads->nhits ||
+                         !roads->hit_begin || !roads->set))
+        return SVT_ERR_ARG;
+    SVT_TRY(launch_fit_plain(bank, *cfg, *roads, n_roads, hit_coord, n_hits, combo_road,
+                             combo_hits, n_combos, *out, d_err, stream));
+    return SVT_OK;
+}
+
+svt_status svt_select(const svt_config *cfg, const svt_roads *roads, int64_t n_roads,
+                      const int32_t *combo_road, const svt_fitrec *rec, int64_t n_combos,
+                      uint8_t *accept, const svt_best *best, int64_t *kept, int64_t kept_cap,
+                      int64_t *d_n_kept, uint64_t *d_err, void *d_work, int64_t work_bytes,
+                      hipStream_t stream) {
+    if (!config_ok(cfg) || !roads || !rec || !best || !d_err || n_roads < 0 || n_combos < 0 ||
+        kept_cap < 0)
+        return SVT_ERR_ARG;
+    if (n_combos > 0 && (!combo_road || !rec->chi2 || !rec->p0 || !rec->p1 || !rec->p2 ||
+                         !accept || !roads->combo_begin))
+        return SVT_ERR_ARG;
+    if (n_roads > 0 && (!best->n_accept || !best->k || !best->p0 || !best->p1 || !best->p2 ||
+                        !best->chi2 || !roads->combo_begin || !roads->ncombo))
+        return SVT_ERR_ARG;
+    if (kept && !d_n_kept) return SVT_ERR_ARG;
+    if (!d_work || work_bytes < svt_select_workspace(n_combos) || !aligned(d_work, kAlign))
+        return SVT_ERR_ARG;
+    int64_t *kb = static_cast<int64_t *>(d_work);
+    const int64_t kbn = ceil_div(n_combos > 0 ? n_combos : 1, kKeptBlock);
+    SVT_TRY(launch_select(*cfg, *roads, n_roads, combo_road, *rec, n_combos, accept, *best, kb,
+                          d_err, stream));
+    if (d_n_kept) {
+        const Sizes nc{n_combos, nullptr, n_combos};
+        SVT_TRY(launch_scan(kb, 0, 1, nc, kKeptBlock, d_n_kept, nullptr, kept ? kept_cap : -1, 2,
+                            d_err, true, stream));
+        if (kept && n_combos > 0)
+            SVT_TRY(launch_kept_write(accept, nc, kbn, kb, kept, kept_cap, d_err, stream));
+    }
+    return SVT_OK;
+}
+
+void svt_set_fused_timing_events(hipEvent_t start, hipEvent_t stop) {
+    g_ev_start = start;
+    g_ev_stop = stop;
+}
+
+static svt_status batch_sequence(const FusedLaunch &f, const BatchWs &w, int64_t word_cap,
+                                 int64_t road_cap, int64_t combo_cap, int64_t *kept,
+                                 int64_t kept_cap, int64_t *d_n_kept, bool timing,
+                                 hipStream_t stream) {
+    const Sizes nw{0, f.d_n_words, word_cap};
+    const Sizes nr{0, f.d_n_roads, road_cap};
+    const Sizes nc{0, f.d_n_combos, combo_cap};
+    uint64_t *err = f.err;
+    SVT_TRY(launch_batch_init(err, w.tile_counter, d_n_kept, stream));
+    SVT_TRY(launch_seg_count(f.words, nw, w.nb, f.cfg.n_layers, w.wb, err, stream));
+    SVT_TRY(launch_scan(w.wb, w.nb, 2, nw, kSegBlockWords, const_cast<int64_t *>(f.d_n_roads),
+                        w.scalars, road_cap, 0, err, false, stream));
+    SVT_TRY(launch_seg_emit(f.words, nw, w.nb, w.wb, f.roads, road_cap, err, stream));
+    SVT_TRY(launch_road_fill(f.words, nw, f.d_n_roads, road_cap, f.roads, f.cfg, nullptr,
+                             nullptr, err, stream));
+    SVT_TRY(launch_combo_count(f.roads, nr, w.rbn, w.rb, err, stream));
+    SVT_TRY(launch_scan(w.rb, 0, 1, nr, kRoadBlock, const_cast<int64_t *>(f.d_n_combos), nullptr,
+                        combo_cap, 1, err, true, stream));
+    SVT_TRY(launch_combo_begin(f.roads, nr, w.rbn, w.rb, f.tune.tile_combos, w.tfr, w.tiles_cap,
+                               &f.best, err, stream));
+    if (timing) SVT_TRY(hipEventRecord(g_ev_start, stream));
+    SVT_TRY(launch_fused(f, stream));
+    if (timing) SVT_TRY(hipEventRecord(g_ev_stop, stream));
+    SVT_TRY(launch_fixup(f, stream));
+    if (d_n_kept) {
+        SVT_TRY(launch_scan(w.kb, 0, 1, nc, kKeptBlock, d_n_kept, nullptr, kept ? kept_cap : -1,
+                            2, err, true, stream));
+        if (kept) SVT_TRY(launch_kept_write(f.accept, nc, w.kbn, w.kb, kept, kept_cap, err, stream));
+    }
+    return SVT_OK;
+}
+
+svt_status svt_process_batch(const svt_fconst *bank, const svt_config *cfg, const svt_tune *tune,
+                             const uint32_t *words, const int64_t *d_n_words, int64_t word_cap,
+                             const svt_roads *roads, int64_t road_cap, const svt_fitrec *rec,
+                             uint8_t *accept, int64_t combo_cap, const svt_best *best,
+                             int64_t *kept, int64_t kept_cap, int64_t *d_n_roads,
+                             int64_t *d_n_combos, int64_t *d_n_kept, uint64_t *d_err,
+                             void *d_work, int64_t work_bytes, int32_t flags,
+                             hipStream_t stream) {
+    if (!config_ok(cfg) || !bank || !words || !d_n_words || !roads || !rec || !best ||
+        !d_n_roads || !d_n_combos || !d_err || word_cap < 0 || road_cap < 0 || combo_cap < 0 ||
+        kept_cap < 0)
+        return SVT_ERR_ARG;
+    if (kept && !d_n_kept) return SVT_ERR_ARG;
+    if (!roads->event || !roads->set || !roads->hit_begin || !roads->nhits ||
+        !roads->combo_begin || !roads->ncombo)
+        return SVT_ERR_ARG;
+    if (!best->n_accept || !best->k || !best->p0 || !best->p1 || !best->p2 || !best->chi2)
+        return SVT_ERR_ARG;
+    if (!rec->p0 || !rec->p1 || !rec->p2 || !rec->chi2 || !accept) return SVT_ERR_ARG;
+    const void *a16[] = {rec->p0, rec->p1, rec->p2, rec->chi2, rec->c0, rec->c1, rec->c2};
+    for (const void *p : a16)
+        if (p && !aligned(p, 16)) return SVT_ERR_ARG;
+    if (!aligned(accept, 4)) return SVT_ERR_ARG;
+    const svt_tune t = resolve_tune(tune);
+    if (!fused_tune_supported(t)) return SVT_ERR_ARG;
+    if (!d_work || work_bytes < svt_batch_workspace(word_cap, road_cap, combo_cap, &t) ||
+        !aligned(d_work, kAlign))
+        return SVT_ERR_ARG;
+    const int cus = num_cus();
+    if (cus <= 0) return SVT_ERR_HIP;
+
+    Carver c{static_cast<char *>(d_work)};
+    const BatchWs w = carve_batch(c, word_cap, road_cap, combo_cap, t.tile_combos);
+    FusedLaunch f{};
+    f.bank = bank;
+    f.cfg = *cfg;
+    f.tune = t;
+    f.words = words;
+    f.d_n_words = d_n_words;
+    f.roads = *roads;
+    f.d_n_roads = d_n_roads;
+    f.d_n_combos = d_n_combos;
+    f.rec = *rec;
+    f.accept = accept;
+    f.best = *best;
+    f.tile_first_road = w.tfr;
+    f.tile_part = w.part;
+    f.kb_counts = w.kb;
+    f.tile_counter = w.tile_counter;
+    f.err = d_err;
+    f.tiles_cap = w.tiles_cap;
+    f.road_cap = road_cap;
+    f.combo_cap = combo_cap;
+    f.num_cus = cus;
+
+    if (!(flags & SVT_BATCH_GRAPH)) {
+        const bool timing = g_ev_start && g_ev_stop;
+        return batch_sequence(f, w, word_cap, road_cap, combo_cap, kept, kept_cap, d_n_kept,
+                              timing, stream);
+    }
+
+    // graph path: key on every value the launch sequence bakes in
+    int dev = 0;
+    SVT_TRY(hipGetDevice(&dev));
+    auto u = [](const void *p) { return static_cast<uint64_t>(reinterpret_cast<uintptr_t>(p)); };
+    GraphKey key = {static_cast<uint64_t>(dev), u(stream), u(bank), u(words), u(d_n_words),
+                    static_cast<uint64_t>(word_cap), static_cast<uint64_t>(road_cap),
+                    static_cast<uint64_t>(combo_cap), static_cast<uint64_t>(kept_cap),
+                    u(roads->event), u(roads->set), u(roads->hit_begin), u(roads->nhits),
+                    u(roads->combo_begin), u(roads->ncombo), u(rec->p0), u(rec->p1), u(rec->p2),
+                    u(rec->chi2), u(rec->c0), u(rec->c1), u(rec->c2), u(accept), u(best->n_accept),
+                    u(best->k), u(best->p0), u(best->p1), u(best->p2), u(best->chi2), u(kept),
+                    u(d_n_roads), u(d_n_combos), u(d_n_kept), u(d_err), u(d_work),
+                    static_cast<uint64_t>(work_bytes), static_cast<uint64_t>(cfg->shift),
+                    static_cast<uint64_t>(cfg->chi2_cut), static_cast<uint64_t>(cfg->max_hits),
+                    static_cast<uint64_t>(cfg->n_sets), static_cast<uint64_t>(t.tile_combos),
+                    static_cast<uint64_t>(t.chunk_roads), static_cast<uint64_t>(t.wg_size),
+                    static_cast<uint64_t>(t.wgs_per_cu)};
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    auto &cache = graph_cache();
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+        SVT_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        svt_status st = batch_sequence(f, w, word_cap, road_cap, combo_cap, kept, kept_cap,
+                                       d_n_kept, false, stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(stream, &g);
+        if (st != SVT_OK || e != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return st != SVT_OK ? st : SVT_ERR_HIP;
+        }
+        hipGraphExec_t ex = nullptr;
+        if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return SVT_ERR_HIP;
+        }
+        it = cache.emplace(key, GraphEntry{g, ex}).first;
+    }
+    SVT_TRY(hipGraphLaunch(it->second.exec, stream));
+    return SVT_OK;
+}
+
+void svt_release_graphs(void) {
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    for (auto &kv : graph_cache()) {
+        (void)hipGraphExecDestroy(kv.second.exec);
+        (void)hipGraphDestroy(kv.second.graph);
+    }
+    graph_cache().clear();
+}
+
+}  // extern "C"

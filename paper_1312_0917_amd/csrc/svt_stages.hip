@@ -1,0 +1,617 @@
+// Stage kernels of libsvt: unpack (segment, emit, road fill), combine (count, scan, list),
+// plain fit (one lane per listed combination), select (cut, best track, kept list).
+//
+// Section II-A of the paper splits the serial code into unpack / combine / fit; these are the
+// one-launch-per-stage GPU forms of those functions, kept simple: they are the baseline the
+// fused persistent pass is compared with and share none of its code beyond the field
+// decoders and scans in svt_common.h.
+#include "svt_common.h"
+
+namespace svt {
+namespace {
+
+__global__ void k_init_err(uint64_t *err) { *err = SVT_NO_ERROR; }
+
+// ---- unpack 1: per 4096-word block, count road starts and event starts ------------------
+// A new event starts where the event tag changes, a new road where either tag changes.
+__global__ __launch_bounds__(kSegThreads) void k_seg_count(const uint32_t *__restrict__ words,
+                                                           Sizes n_words_s, int32_t n_layers,
+                                                           int64_t *wb_counts, int64_t nb_stride,
+                                                           uint64_t *err) {
+    __shared__ int64_t tmp[kSegThreads / kWaveSize + 1];
+    const int64_t n = load_size(n_words_s);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n_words_s.dev && *n_words_s.dev > n_words_s.cap)
+        report(err, SVT_ERRCLASS_CAPACITY, 3);
+    const int64_t nb = (n + kSegBlockWords - 1) / kSegBlockWords;
+    const bool aligned = (reinterpret_cast<uintptr_t>(words) & 15) == 0;
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const int64_t base = b * kSegBlockWords + static_cast<int64_t>(threadIdx.x) * kSegWordsPerThread;
+        uint32_t w[kSegWordsPerThread];
+        if (aligned && base + kSegWordsPerThread <= n) {
+            const uint4 *p = reinterpret_cast<const uint4 *>(words + base);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                uint4 t = p[v];
+                w[4 * v] = t.x; w[4 * v + 1] = t.y; w[4 * v + 2] = t.z; w[4 * v + 3] = t.w;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < kSegWordsPerThread; ++e) w[e] = (base + e < n) ? words[base + e] : 0u;
+        }
+        uint32_t prev = (base > 0 && base <= n) ? words[base - 1] : 0u;
+        int64_t nr = 0, ne = 0;
+        int64_t bad = -1;
+#pragma unroll
+        for (int e = 0; e < kSegWordsPerThread; ++e) {
+            const int64_t i = base + e;
+            if (i < n) {
+                const uint32_t x = w[e];
+                const bool first = (i == 0);
+                nr += (first || w_tags(x) != w_tags(prev)) ? 1 : 0;
+                ne += (first || w_etag(x) != w_etag(prev)) ? 1 : 0;
+                if (bad < 0 && static_cast<int32_t>(w_layer(x)) >= n_layers) bad = i;
+                prev = x;
+            }
+        }
+        if (bad >= 0) report(err, SVT_ERRCLASS_LAYER, static_cast<uint64_t>(bad));
+        const int64_t br = block_sum<int64_t, kSegThreads>(nr, tmp);
+        const int64_t be = block_sum<int64_t, kSegThreads>(ne, tmp);
+        if (threadIdx.x == 0) {
+            wb_counts[b] = br;
+            wb_counts[nb_stride + b] = be;
+        }
+    }
+}
+
+// ---- single-workgroup in-place exclusive scan, one workgroup per column ------------------
+__global__ __launch_bounds__(kScanThreads) void k_scan(int64_t *data, int64_t col_stride,
+                                                       Sizes n_s, int64_t div, int64_t *tot0,
+                                                       int64_t *tot1, int64_t cap0,
+                                                       uint32_t cap_index, uint64_t *err,
+                                                       int32_t skip_if_error) {
+    __shared__ int64_t tmp[kScanThreads / kWaveSize + 1];
+    constexpr int kItems = 4;
+    if (skip_if_error && has_error(err)) {
+        if (threadIdx.x == 0) {
+            int64_t *tot = blockIdx.x == 0 ? tot0 : tot1;
+            if (tot) *tot = -1;
+        }
+        return;
+    }
+    const int64_t n = (load_size(n_s) + div - 1) / div;
+    int64_t *col = data + blockIdx.x * col_stride;
+    int64_t carry = 0;
+    for (int64_t base = 0; base < n; base += static_cast<int64_t>(kScanThreads) * kItems) {
+        const int64_t i0 = base + static_cast<int64_t>(threadIdx.x) * kItems;
+        int64_t v[kItems];
+        int64_t s = 0;
+#pragma unroll
+        for (int e = 0; e < kItems; ++e) {
+            v[e] = (i0 + e < n) ? col[i0 + e] : 0;
+            s += v[e];
+        }
+        int64_t total;
+        int64_t ex = block_excl_scan<int64_t, kScanThreads>(s, tmp, total);
+        int64_t run = carry + ex;
+#pragma unroll
+        for (int e = 0; e < kItems; ++e) {
+            if (i0 + e < n) col[i0 + e] = run;
+            run += v[e];
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) {
+        int64_t *tot = blockIdx.x == 0 ? tot0 : tot1;
+        if (tot) *tot = carry;
+        if (blockIdx.x == 0 && cap0 >= 0 && carry > cap0)
+            report(err, SVT_ERRCLASS_CAPACITY, cap_index);
+    }
+}
+
+// ---- unpack 2: write each road's first word, tag and event ordinal -----------------------
+__global__ __launch_bounds__(kSegThreads) void k_seg_emit(const uint32_t *__restrict__ words,
+                                                          Sizes n_words_s,
+                                                          const int64_t *__restrict__ wb_prefix,
+                                                          int64_t nb_stride, svt_roads roads,
+                                                          int64_t road_cap, uint64_t *err) {
+    __shared__ int64_t tmp[kSegThreads / kWaveSize + 1];
+    if (has_error(err)) return;
+    const int64_t n = load_size(n_words_s);
+    const int64_t nb = (n + kSegBlockWords - 1) / kSegBlockWords;
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const int64_t base = b * kSegBlockWords + static_cast<int64_t>(threadIdx.x) * kSegWordsPerThread;
+        uint32_t w[kSegWordsPerThread];
+#pragma unroll
+        for (int e = 0; e < kSegWordsPerThread; ++e) w[e] = (base + e < n) ? words[base + e] : 0u;
+        const uint32_t prev0 = (base > 0 && base <= n) ? words[base - 1] : 0u;
+        uint32_t flags = 0;  // bit 2e: new road, bit 2e+1: new event
+        int64_t nr = 0, ne = 0;
+        uint32_t prev = prev0;
+#pragma unroll
+        for (int e = 0; e < kSegWordsPerThread; ++e) {
+            const int64_t i = base + e;
+            if (i < n) {
+                const bool first = (i == 0);
+                const bool r = first || w_tags(w[e]) != w_tags(prev);
+                const bool v = first || w_etag(w[e]) != w_etag(prev);
+                flags |= (r ? 1u : 0u) << (2 * e);
+                flags |= (v ? 1u : 0u) << (2 * e + 1);
+                nr += r;
+                ne += v;
+                prev = w[e];
+            }
+        }
+        int64_t tr, te;
+        int64_t rc = block_excl_scan<int64_t, kSegThreads>(nr, tmp, tr) + wb_prefix[b];
+        int64_t ec = block_excl_scan<int64_t, kSegThreads>(ne, tmp, te) + wb_prefix[nb_stride + b];
+#pragma unroll
+        for (int e = 0; e < kSegWordsPerThread; ++e) {
+            const int64_t i = base + e;
+            if (i < n) {
+                if (flags & (2u << (2 * e))) ++ec;
+                if (flags & (1u << (2 * e))) {
+                    const int64_t r = rc++;
+                    if (r < road_cap) {
+                        roads.hit_begin[r] = i;
+                        roads.set[r] = static_cast<int32_t>(w_rtag(w[e]));
+                        roads.event[r] = static_cast<int32_t>(ec - 1);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---- unpack 3: per road, count hits per layer, check, regroup coordinates by layer -------
+__global__ __launch_bounds__(kRoadBlock) void k_road_fill(const uint32_t *__restrict__ words,
+                                                          Sizes n_words_s,
+                                                          const int64_t *d_n_roads,
+                                                          int64_t road_cap, svt_roads roads,
+                                                          svt_config cfg, int16_t *hit_coord,
+                                                          uint64_t *err) {
+    if (has_error(err)) return;
+    const int64_t n = load_size(n_words_s);
+    const int64_t nr_all = *d_n_roads;
+    if (nr_all > road_cap || nr_all < 0) return;  // capacity error already reported
+    const int64_t nr = nr_all;
+    const int64_t max_len = static_cast<int64_t>(cfg.n_layers) * cfg.max_hits;
+    for (int64_t r = gtid(); r < nr; r += gstride()) {
+        const int64_t b = roads.hit_begin[r];
+        const int64_t e = (r + 1 < nr_all) ? roads.hit_begin[r + 1] : n;
+        const int64_t len = e - b;
+        if (len <= 0 || len > max_len || b < 0 || e > n) {
+            report(err, SVT_ERRCLASS_HITS, static_cast<uint64_t>(r));
+            continue;
+        }
+        uint64_t cnt = 0;  // 8 bits per layer
+        for (int64_t i = b; i < e; ++i) {
+            const uint32_t l = w_layer(words[i]);
+            if (l < SVT_N_LAYERS) cnt += 1ull << (8 * l);
+        }
+        bool over = false;
+        uint32_t packed = 0;
+        for (int l = 0; l < SVT_N_LAYERS; ++l) {
+            const uint32_t c = static_cast<uint32_t>((cnt >> (8 * l)) & 0xFF);
+            over |= c > static_cast<uint32_t>(cfg.max_hits);
+            packed |= (c & 0xFu) << (4 * l);
+        }
+        if (over) {
+            report(err, SVT_ERRCLASS_HITS, static_cast<uint64_t>(r));
+            continue;
+        }
+        if (static_cast<uint32_t>(roads.set[r]) >= static_cast<uint32_t>(cfg.n_sets))
+            report(err, SVT_ERRCLASS_SET, static_cast<uint64_t>(r));
+        roads.nhits[r] = packed;
+        if (hit_coord) {
+            uint32_t off[SVT_N_LAYERS];
+            uint32_t run = 0;
+            for (int l = 0; l < SVT_N_LAYERS; ++l) {
+                off[l] = run;
+                run += nh_of(packed, l);
+            }
+            for (int64_t i = b; i < e; ++i) {
+                const uint32_t w = words[i];
+                const uint32_t l = w_layer(w);
+                if (l >= SVT_N_LAYERS) continue;
+                uint32_t o = 0;
+                // select off[l] without dynamic register indexing
+                for (int k = 0; k < SVT_N_LAYERS; ++k)
+                    if (static_cast<uint32_t>(k) == l) { o = off[k]; off[k] = o + 1; }
+                hit_coord[b + o] = static_cast<int16_t>(w_coord(w));
+            }
+        }
+    }
+}
+
+// ---- combine 1: combinations per road and per-block sums ---------------------------------
+__global__ __launch_bounds__(kRoadBlock) void k_combo_count(svt_roads roads, Sizes n_roads_s,
+                                                            int64_t *rb_sums, uint64_t *err) {
+    __shared__ int64_t tmp[kRoadBlock / kWaveSize + 1];
+    if (has_error(err)) return;
+    const int64_t nr = load_size(n_roads_s);
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kRoadBlock + threadIdx.x;
+    if (static_cast<int64_t>(blockIdx.x) * kRoadBlock >= nr) return;
+    int64_t c = 0;
+    if (r < nr) {
+        const uint32_t p = roads.nhits[r];
+        c = 1;
+        for (int l = 0; l < SVT_N_LAYERS; ++l) c *= nh_of(p, l);
+        roads.ncombo[r] = static_cast<int32_t>(c);
+    }
+    const int64_t s = block_sum<int64_t, kRoadBlock>(c, tmp);
+    if (threadIdx.x == 0) rb_sums[blockIdx.x] = s;
+}
+
+// ---- combine 2: combo_begin, tile marks, defaults of roads without combinations ----------
+__global__ __launch_bounds__(kRoadBlock) void k_combo_begin(svt_roads roads, Sizes n_roads_s,
+                                                            const int64_t *rb_prefix,
+                                                            int64_t tile_combos,
+                                                            int32_t *tile_first_road,
+                                                            int64_t tiles_cap, svt_best best,
+                                                            int32_t write_defaults,
+                                                            uint64_t *err) {
+    __shared__ int64_t tmp[kRoadBlock / kWaveSize + 1];
+    if (has_error(err)) return;
+    const int64_t nr = load_size(n_roads_s);
+    if (static_cast<int64_t>(blockIdx.x) * kRoadBlock >= nr) return;
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kRoadBlock + threadIdx.x;
+    const int64_t c = (r < nr) ? roads.ncombo[r] : 0;
+    int64_t tot;
+    const int64_t begin = block_excl_scan<int64_t, kRoadBlock>(c, tmp, tot) + rb_prefix[blockIdx.x];
+    if (r >= nr) return;
+    roads.combo_begin[r] = begin;
+    if (tile_combos > 0 && c > 0) {
+        // this road holds the first combination of every tile that starts inside it
+        for (int64_t t = (begin + tile_combos - 1) / tile_combos; t * tile_combos < begin + c; ++t)
+            if (t < tiles_cap) tile_first_road[t] = static_cast<int32_t>(r);
+    }
+    if (write_defaults && c == 0) {
+        best.n_accept[r] = 0;
+        best.k[r] = -1;
+        best.p0[r] = INT32_MIN;
+        best.p1[r] = INT32_MIN;
+        best.p2[r] = INT32_MIN;
+        best.chi2[r] = INT64_MAX;
+    }
+}
+
+// ---- combine 3 (plain path): list every combination --------------------------------------
+__global__ __launch_bounds__(kRoadBlock) void k_materialize(svt_roads roads, int64_t n_roads,
+                                                            const int64_t *d_n_combos,
+                                                            int64_t combo_cap,
+                                                            int32_t *combo_road,
+                                                            uint32_t *combo_hits,
+                                                            uint64_t *err) {
+    __shared__ int64_t s_begin[kRoadBlock + 1];
+    __shared__ uint32_t s_nh[kRoadBlock];
+    if (has_error(err)) return;
+    const int64_t total = *d_n_combos;
+    if (total > combo_cap) return;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kRoadBlock;
+    if (r0 >= n_roads) return;
+    const int nloc = static_cast<int>((n_roads - r0) < kRoadBlock ? (n_roads - r0) : kRoadBlock);
+    if (threadIdx.x < nloc) {
+        s_begin[threadIdx.x] = roads.combo_begin[r0 + threadIdx.x];
+        s_nh[threadIdx.x] = roads.nhits[r0 + threadIdx.x];
+    }
+    if (threadIdx.x == 0) {
+        const int64_t rl = r0 + nloc - 1;
+        s_begin[nloc] = roads.combo_begin[rl] + roads.ncombo[rl];
+    }
+    __syncthreads();
+    const int64_t c_lo = s_begin[0], c_hi = s_begin[nloc];
+    for (int64_t c = c_lo + threadIdx.x; c < c_hi; c += kRoadBlock) {
+        int lo = 0, hi = nloc - 1;  // last road with begin <= c
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_begin[mid] <= c) lo = mid; else hi = mid - 1;
+        }
+        uint32_t k = static_cast<uint32_t>(c - s_begin[lo]);
+        const uint32_t p = s_nh[lo];
+        uint32_t h[SVT_N_LAYERS];
+        for (int l = SVT_N_LAYERS - 1; l >= 0; --l) {  // layer 0 most significant
+            const uint32_t nl = nh_of(p, l);
+            h[l] = k % nl;
+            k /= nl;
+        }
+        uint32_t packed = 0;
+        for (int l = 0; l < SVT_N_LAYERS; ++l) packed |= h[l] << (4 * l);
+        if (combo_road) combo_road[c] = static_cast<int32_t>(r0 + lo);
+        if (combo_hits) combo_hits[c] = packed;
+    }
+}
+
+// ---- plain fit: one lane per listed combination, 64-bit accumulation -----------------------
+__global__ __launch_bounds__(256) void k_fit_plain(const svt_fconst *__restrict__ bank,
+                                                   svt_config cfg, svt_roads roads,
+                                                   int64_t n_roads,
+                                                   const int16_t *__restrict__ hit_coord,
+                                                   int64_t n_hits,
+                                                   const int32_t *__restrict__ combo_road,
+                                                   const uint32_t *__restrict__ combo_hits,
+                                                   int64_t n_combos, svt_fitrec out,
+                                                   uint64_t *err) {
+    for (int64_t i = gtid(); i < n_combos; i += gstride()) {
+        const int32_t r = combo_road[i];
+        if (r < 0 || r >= n_roads) { report(err, SVT_ERRCLASS_INDEX, i); continue; }
+        const uint32_t ph = combo_hits[i];
+        const uint32_t pn = roads.nhits[r];
+        const int64_t hb = roads.hit_begin[r];
+        const int32_t s = roads.set[r];
+        bool ok = (s >= 0 && s < cfg.n_sets);
+        int32_t x[SVT_N_LAYERS];
+        int64_t off = hb;
+        for (int l = 0; l < SVT_N_LAYERS; ++l) {
+            const uint32_t d = (ph >> (4 * l)) & 0xFu;
+            const uint32_t nl = nh_of(pn, l);
+            const int64_t idx = off + d;
+            ok &= (d < nl) && idx >= 0 && idx < n_hits;
+            x[l] = ok ? hit_coord[idx] : 0;
+            off += nl;
+        }
+        if (!ok) { report(err, SVT_ERRCLASS_INDEX, i); continue; }
+        const svt_fconst &F = bank[s];
+        int32_t v[6];
+        for (int j = 0; j < 6; ++j) {
+            int64_t a = 0;
+            for (int l = 0; l < SVT_N_LAYERS; ++l)
+                a += static_cast<int64_t>(F.f[j][l]) * static_cast<int64_t>(x[l]);
+            a += static_cast<int64_t>(F.q[j]);
+            v[j] = static_cast<int32_t>(a >> cfg.shift);  // arithmetic shift = floor
+        }
+        const int64_t chi2 = static_cast<int64_t>(v[3]) * v[3] +
+                             static_cast<int64_t>(v[4]) * v[4] +
+                             static_cast<int64_t>(v[5]) * v[5];
+        out.p0[i] = v[0];
+        out.p1[i] = v[1];
+        out.p2[i] = v[2];
+        out.chi2[i] = chi2;
+        if (out.c0) out.c0[i] = v[3];
+        if (out.c1) out.c1[i] = v[4];
+        if (out.c2) out.c2[i] = v[5];
+    }
+}
+
+// ---- select: cut, per-road best key (chi2 << 15 | k) and counts, kept-block counts -------
+__global__ void k_best_init(svt_best best, int64_t n_roads) {
+    for (int64_t r = gtid(); r < n_roads; r += gstride()) {
+        reinterpret_cast<uint64_t *>(best.chi2)[r] = UINT64_MAX;
+        best.n_accept[r] = 0;
+    }
+}
+
+__global__ __launch_bounds__(kSegThreads) void k_select_mark(svt_config cfg, svt_roads roads,
+                                                             int64_t n_roads,
+                                                             const int32_t *__restrict__ combo_road,
+                                                             const int64_t *__restrict__ chi2,
+                                                             int64_t n_combos, uint8_t *accept,
+                                                             svt_best best, int64_t *kb_counts,
+                                                             uint64_t *err) {
+    __shared__ int64_t tmp[kSegThreads / kWaveSize + 1];
+    const int64_t nb = (n_combos + kKeptBlock - 1) / kKeptBlock;
+    uint64_t *key = reinterpret_cast<uint64_t *>(best.chi2);
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const int64_t base = b * kKeptBlock + static_cast<int64_t>(threadIdx.x) * 16;
+        int64_t cnt = 0;
+        for (int e = 0; e < 16; ++e) {
+            const int64_t i = base + e;
+            if (i >= n_combos) break;
+            const int64_t c2 = chi2[i];
+            const bool acc = c2 <= cfg.chi2_cut;
+            accept[i] = acc ? 1 : 0;
+            if (acc) {
+                ++cnt;
+                const int32_t r = combo_road[i];
+                if (r < 0 || r >= n_roads) { report(err, SVT_ERRCLASS_INDEX, i); continue; }
+                const int64_t k = i - roads.combo_begin[r];
+                if (k < 0 || k >= (1 << kKeyKBits) || c2 < 0) {
+                    report(err, SVT_ERRCLASS_INDEX, i);
+                    continue;
+                }
+                const uint64_t kv = best_key(c2, static_cast<uint32_t>(k));
+                atomicMin(reinterpret_cast<unsigned long long *>(key + r), kv);
+                atomicAdd(best.n_accept + r, 1);
+            }
+        }
+        const int64_t s = block_sum<int64_t, kSegThreads>(cnt, tmp);
+        if (threadIdx.x == 0 && kb_counts) kb_counts[b] = s;
+    }
+}
+
+__global__ void k_best_finalize(svt_roads roads, int64_t n_roads, svt_fitrec rec,
+                                int64_t n_combos, svt_best best, int64_t cut) {
+    for (int64_t r = gtid(); r < n_roads; r += gstride()) {
+        uint64_t key = reinterpret_cast<uint64_t *>(best.chi2)[r];
+        if (key != UINT64_MAX && (key >> kKeyKBits) == kKeyChiMax) {
+            // saturated key: exact scan of the road's records (chi2 >= 2^49 - 1 only)
+            const int64_t cb = roads.combo_begin[r];
+            const int64_t nc = roads.ncombo[r];
+            uint64_t bchi = UINT64_MAX;
+            int64_t bk = 0;
+            for (int64_t k = 0; k < nc && cb + k < n_combos; ++k) {
+                const int64_t c2 = rec.chi2[cb + k];
+                if (c2 <= cut && c2 >= 0 && static_cast<uint64_t>(c2) < bchi) {
+                    bchi = static_cast<uint64_t>(c2);
+                    bk = k;
+                }
+            }
+            if (bchi != UINT64_MAX) {
+                const int64_t g = cb + bk;
+                best.k[r] = static_cast<int32_t>(bk);
+                best.chi2[r] = static_cast<int64_t>(bchi);
+                best.p0[r] = rec.p0[g];
+                best.p1[r] = rec.p1[g];
+                best.p2[r] = rec.p2[g];
+                continue;
+            }
+            key = UINT64_MAX;
+        }
+        if (key == UINT64_MAX) {
+            best.k[r] = -1;
+            best.p0[r] = INT32_MIN;
+            best.p1[r] = INT32_MIN;
+            best.p2[r] = INT32_MIN;
+            best.chi2[r] = INT64_MAX;
+        } else {
+            const int32_t k = static_cast<int32_t>(key & ((1u << kKeyKBits) - 1));
+            const int64_t g = roads.combo_begin[r] + k;
+            best.k[r] = k;
+            best.chi2[r] = static_cast<int64_t>(key >> kKeyKBits);
+            const bool in = g >= 0 && g < n_combos;
+            best.p0[r] = in ? rec.p0[g] : INT32_MIN;
+            best.p1[r] = in ? rec.p1[g] : INT32_MIN;
+            best.p2[r] = in ? rec.p2[g] : INT32_MIN;
+        }
+    }
+}
+
+// ---- kept list: ascending indices of accepted combinations -------------------------------
+__global__ __launch_bounds__(kSegThreads) void k_kept_write(const uint8_t *__restrict__ accept,
+                                                            Sizes n_s,
+                                                            const int64_t *__restrict__ kb_prefix,
+                                                            int64_t *kept, int64_t kept_cap,
+                                                            uint64_t *err) {
+    __shared__ int64_t tmp[kSegThreads / kWaveSize + 1];
+    const int64_t n = load_size(n_s);
+    const int64_t nb = (n + kKeptBlock - 1) / kKeptBlock;
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const int64_t base = b * kKeptBlock + static_cast<int64_t>(threadIdx.x) * 16;
+        uint32_t bits = 0;
+        for (int e = 0; e < 16; ++e) {
+            const int64_t i = base + e;
+            if (i < n && accept[i]) bits |= 1u << e;
+        }
+        int64_t tot;
+        int64_t pos = block_excl_scan<int64_t, kSegThreads>(__popc(bits), tmp, tot) + kb_prefix[b];
+        while (bits) {
+            const int e = __ffs(bits) - 1;
+            bits &= bits - 1;
+            if (pos < kept_cap) kept[pos] = base + e;
+            ++pos;
+        }
+    }
+    (void)err;
+}
+
+inline int64_t clamp_grid(int64_t blocks, int64_t maxb) {
+    if (blocks < 1) return 1;
+    return blocks < maxb ? blocks : maxb;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+hipError_t launch_init_err(uint64_t *d_err, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_err, dim3(1), dim3(1), 0, s, d_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_count(const uint32_t *words, Sizes n_words, int64_t grid_blocks,
+                            int32_t n_layers, int64_t *wb_counts, uint64_t *err, hipStream_t s) {
+    const int64_t g = clamp_grid(grid_blocks, 1 << 16);
+    hipLaunchKernelGGL(k_seg_count, dim3(g), dim3(kSegThreads), 0, s, words, n_words, n_layers,
+                       wb_counts, grid_blocks, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(int64_t *data, int64_t col_stride, int ncols, Sizes n, int64_t div,
+                       int64_t *tot0, int64_t *tot1, int64_t cap0, uint32_t cap_index,
+                       uint64_t *err, bool skip_if_error, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan, dim3(ncols), dim3(kScanThreads), 0, s, data, col_stride, n, div,
+                       tot0, tot1, cap0, cap_index, err, static_cast<int32_t>(skip_if_error));
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_emit(const uint32_t *words, Sizes n_words, int64_t grid_blocks,
+                           const int64_t *wb_prefix, const svt_roads &roads, int64_t road_cap,
+                           uint64_t *err, hipStream_t s) {
+    const int64_t g = clamp_grid(grid_blocks, 1 << 16);
+    hipLaunchKernelGGL(k_seg_emit, dim3(g), dim3(kSegThreads), 0, s, words, n_words, wb_prefix,
+                       grid_blocks, roads, road_cap, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_road_fill(const uint32_t *words, Sizes n_words, const int64_t *d_n_roads,
+                            int64_t road_cap, const svt_roads &roads, const svt_config &cfg,
+                            int16_t *hit_coord, int64_t *rb_sums, uint64_t *err,
+                            hipStream_t s) {
+    (void)rb_sums;
+    const int64_t g = clamp_grid((road_cap + kRoadBlock - 1) / kRoadBlock, 8192);
+    hipLaunchKernelGGL(k_road_fill, dim3(g), dim3(kRoadBlock), 0, s, words, n_words, d_n_roads,
+                       road_cap, roads, cfg, hit_coord, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_combo_count(const svt_roads &roads, Sizes n_roads, int64_t grid_blocks,
+                              int64_t *rb_sums, uint64_t *err, hipStream_t s) {
+    const int64_t g = grid_blocks < 1 ? 1 : grid_blocks;
+    hipLaunchKernelGGL(k_combo_count, dim3(g), dim3(kRoadBlock), 0, s, roads, n_roads, rb_sums,
+                       err);
+    return hipGetLastError();
+}
+
+hipError_t launch_combo_begin(const svt_roads &roads, Sizes n_roads, int64_t grid_blocks,
+                              const int64_t *rb_prefix, int64_t tile_combos,
+                              int32_t *tile_first_road, int64_t tiles_cap,
+                              const svt_best *best_defaults, uint64_t *err, hipStream_t s) {
+    const int64_t g = grid_blocks < 1 ? 1 : grid_blocks;
+    svt_best b = best_defaults ? *best_defaults : svt_best{};
+    hipLaunchKernelGGL(k_combo_begin, dim3(g), dim3(kRoadBlock), 0, s, roads, n_roads, rb_prefix,
+                       tile_combos, tile_first_road, tiles_cap, b,
+                       static_cast<int32_t>(best_defaults != nullptr), err);
+    return hipGetLastError();
+}
+
+hipError_t launch_materialize(const svt_roads &roads, int64_t n_roads, const int64_t *d_n_combos,
+                              int64_t combo_cap, int32_t *combo_road, uint32_t *combo_hits,
+                              uint64_t *err, hipStream_t s) {
+    if (n_roads <= 0 || (!combo_road && !combo_hits)) return hipSuccess;
+    const int64_t g = (n_roads + kRoadBlock - 1) / kRoadBlock;
+    hipLaunchKernelGGL(k_materialize, dim3(g), dim3(kRoadBlock), 0, s, roads, n_roads, d_n_combos,
+                       combo_cap, combo_road, combo_hits, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_fit_plain(const svt_fconst *bank, const svt_config &cfg,
+                            const svt_roads &roads, int64_t n_roads, const int16_t *hit_coord,
+                            int64_t n_hits, const int32_t *combo_road,
+                            const uint32_t *combo_hits, int64_t n_combos, const svt_fitrec &out,
+                            uint64_t *err, hipStream_t s) {
+    if (n_combos <= 0) return hipSuccess;
+    const int64_t g = clamp_grid((n_combos + 255) / 256, 1 << 20);
+    hipLaunchKernelGGL(k_fit_plain, dim3(g), dim3(256), 0, s, bank, cfg, roads, n_roads,
+                       hit_coord, n_hits, combo_road, combo_hits, n_combos, out, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const svt_config &cfg, const svt_roads &roads, int64_t n_roads,
+                         const int32_t *combo_road, const svt_fitrec &rec, int64_t n_combos,
+                         uint8_t *accept, const svt_best &best, int64_t *kb_counts,
+                         uint64_t *err, hipStream_t s) {
+    if (n_roads > 0) {
+        const int64_t g = clamp_grid((n_roads + 255) / 256, 1 << 16);
+        hipLaunchKernelGGL(k_best_init, dim3(g), dim3(256), 0, s, best, n_roads);
+    }
+    if (n_combos > 0) {
+        const int64_t g = clamp_grid((n_combos + kKeptBlock - 1) / kKeptBlock, 1 << 16);
+        hipLaunchKernelGGL(k_select_mark, dim3(g), dim3(kSegThreads), 0, s, cfg, roads, n_roads,
+                           combo_road, rec.chi2, n_combos, accept, best, kb_counts, err);
+    }
+    if (n_roads > 0) {
+        const int64_t g = clamp_grid((n_roads + 255) / 256, 1 << 16);
+        hipLaunchKernelGGL(k_best_finalize, dim3(g), dim3(256), 0, s, roads, n_roads, rec,
+                           n_combos, best, cfg.chi2_cut);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_kept_write(const uint8_t *accept, Sizes n_combos, int64_t grid_blocks,
+                             const int64_t *kb_prefix, int64_t *kept, int64_t kept_cap,
+                             uint64_t *err, hipStream_t s) {
+    const int64_t g = clamp_grid(grid_blocks, 1 << 16);
+    hipLaunchKernelGGL(k_kept_write, dim3(g), dim3(kSegThreads), 0, s, accept, n_combos,
+                       kb_prefix, kept, kept_cap, err);
+    return hipGetLastError();
+}
+
+}  // namespace svt

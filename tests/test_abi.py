@@ -1,0 +1,109 @@
+"""The C-ABI library loads and exports every entry point the public header declares.
+
+CPU-only: no call here reaches a GPU (host-side helpers and argument checks only).
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1312_0917_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "svt.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(svt_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_five_stages():
+    names = declared_functions()
+    for n in ["svt_unpack", "svt_combine", "svt_fit", "svt_select", "svt_process_batch"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported():
+    lib = L.load()
+    names = declared_functions()
+    assert names, "no declarations parsed"
+    for n in names:
+        assert hasattr(lib, n), f"{n} missing from libsvt.so"
+    assert sorted(L.exported_symbols()) == names
+
+
+def test_abi_version_and_struct_sizes():
+    lib = L.load()
+    assert lib.svt_abi_version() == 1
+    assert ctypes.sizeof(L.svt_config) == 24
+    assert ctypes.sizeof(L.svt_tune) == 16
+    rec = L.pack_bank(__import__("numpy").zeros((2, 6, 5), "int16"),
+                      __import__("numpy").zeros((2, 6), "int32"))
+    assert rec.shape == (2, 88)
+
+
+def test_error_word_decoding():
+    assert L.error_decode(L.SVT_NO_ERROR) == (L.SVT_OK, -1)
+    assert L.error_decode((1 << 56) | 17) == (L.SVT_ERR_LAYER, 17)
+    assert L.error_decode((2 << 56) | 5) == (L.SVT_ERR_HITS, 5)
+    assert L.error_decode((3 << 56) | 9) == (L.SVT_ERR_SET, 9)
+    assert L.error_decode((4 << 56) | 1) == (L.SVT_ERR_CAPACITY, 1)
+    assert L.error_decode((5 << 56) | 3) == (L.SVT_ERR_ARG, 3)
+    # ordering of the packed word is the precedence order
+    assert (1 << 56) | 1000 < (2 << 56) | 0
+
+
+def test_workspace_sizes_are_aligned_and_monotone():
+    for n in [0, 1, 4095, 4096, 4097, 10**6]:
+        a = L.svt_unpack_workspace(n)
+        assert a > 0 and a % 256 == 0
+        assert L.svt_unpack_workspace(n + 4096) >= a
+    assert L.svt_unpack_workspace(-1) == -1
+    t = L.make_tune(8192, 64, 256, 4)
+    assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, t) > 0
+    assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, L.make_tune(1000, 64, 256, 4)) == -1
+    assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, L.make_tune(8192, 48, 256, 4)) == -1
+
+
+def test_host_argument_checks_reject_without_launching():
+    lib = L.load()
+    cfg = L.make_config()
+    roads = L.svt_roads()
+    # null error word / sizes: rejected before any HIP call
+    assert lib.svt_unpack(None, 0, ctypes.byref(cfg), ctypes.byref(roads), 0, None, None, None,
+                          None, 0, None) == L.SVT_ERR_ARG
+    bad = L.make_config(n_layers=4)
+    assert lib.svt_combine(ctypes.byref(roads), 0, ctypes.byref(bad), None, None, 0, None, None,
+                           None, 0, None) == L.SVT_ERR_ARG
+    bad_shift = L.make_config(shift=0)
+    rec = L.svt_fitrec()
+    assert lib.svt_fit(None, ctypes.byref(bad_shift), ctypes.byref(roads), 0, None, 0, None,
+                       None, 0, ctypes.byref(rec), None, None) == L.SVT_ERR_ARG
+    best = L.svt_best()
+    assert lib.svt_select(ctypes.byref(cfg), ctypes.byref(roads), -1, None, ctypes.byref(rec), 0,
+                          None, ctypes.byref(best), None, 0, None, None, None, 0,
+                          None) == L.SVT_ERR_ARG
+    tune = L.make_tune()
+    assert lib.svt_process_batch(None, ctypes.byref(cfg), ctypes.byref(tune), None, None, 0,
+                                 ctypes.byref(roads), 0, ctypes.byref(rec), None, 0,
+                                 ctypes.byref(best), None, 0, None, None, None, None, None, 0,
+                                 0, None) == L.SVT_ERR_ARG
+
+
+def test_product_path_does_not_import_the_oracle():
+    import sys
+    import importlib
+    for m in list(sys.modules):
+        if m == "oracle" or m.startswith("oracle."):
+            pass
+    src_dir = os.path.join(ROOT, "paper_1312_0917_amd")
+    for fn in os.listdir(src_dir):
+        if fn.endswith(".py"):
+            text = open(os.path.join(src_dir, fn)).read()
+            assert "import oracle" not in text and "from oracle" not in text, fn
+    for fn in os.listdir(os.path.join(src_dir, "csrc")):
+        text = open(os.path.join(src_dir, "csrc", fn)).read()
+        assert "svt_oracle" not in text and "ora_" not in text, fn

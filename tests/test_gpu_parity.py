@@ -1,0 +1,232 @@
+"""GPU parity: both HIP paths against the CPU oracle, bit for bit (integer outputs).
+
+Every input is drawn by the seeded generator; every expected value comes from the oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import (BATCH_KEYS, PLAIN_KEYS, compare, gpu_cfg, run_batch, run_plain, to_np)
+from tiny import pack, random_bank, random_events, stream
+
+from paper_1312_0917_amd import _lib as L
+from paper_1312_0917_amd import pipeline as P
+from paper_1312_0917_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+CFG = oracle.make_config(chi2_cut=synth.DEFAULT_CHI2_CUT)
+TUNES = [L.make_tune(4096, 16, 256, 2), L.make_tune(8192, 64, 256, 4),
+         L.make_tune(16384, 32, 512, 2), L.make_tune(65536, 64, 512, 1)]
+
+
+@pytest.fixture(scope="module")
+def samples(bank):
+    out = {}
+    for c in ["c1", "c2", "c3"]:
+        s = synth.make_sample(c, bank=bank)
+        out[c] = (s, oracle.run(s.words, bank.f, bank.q, CFG))
+    return out
+
+
+@pytest.mark.parametrize("config", ["c1", "c2", "c3"])
+def test_plain_path_matches_oracle(samples, bank, config):
+    s, ref = samples[config]
+    got = run_plain(s.words, bank.f, bank.q, CFG)
+    compare(ref, got, PLAIN_KEYS, f"plain {config}")
+
+
+@pytest.mark.parametrize("config", ["c1", "c2", "c3"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_path_matches_oracle(samples, bank, config, graph):
+    s, ref = samples[config]
+    got, runner = run_batch(s.words, bank.f, bank.q, CFG, ref=ref, graph=graph)
+    compare(ref, got, BATCH_KEYS, f"batch {config} graph={graph}")
+    if graph:  # a replay of the captured graph gives the same bytes
+        runner.run()
+        compare(ref, runner.result(), BATCH_KEYS, f"batch {config} replay")
+    L.svt_release_graphs()
+
+
+@pytest.mark.parametrize("ti", range(len(TUNES)))
+def test_batch_every_tune_is_bit_identical(samples, bank, ti):
+    """Schedule independence: every tile / chunk / workgroup shape writes the same bytes."""
+    s, ref = samples["c3"]
+    got, _ = run_batch(s.words, bank.f, bank.q, CFG, ref=ref, tune=TUNES[ti], graph=False)
+    compare(ref, got, BATCH_KEYS, f"c3 tune {ti}")
+
+
+def test_batch_repeats_are_deterministic(samples, bank):
+    s, ref = samples["c2"]
+    got, runner = run_batch(s.words, bank.f, bank.q, CFG, ref=ref, graph=True)
+    first = {k: to_np(v).copy() for k, v in got.items() if isinstance(v, torch.Tensor)}
+    for _ in range(5):
+        runner.run()
+        again = runner.result()
+        for k, v in first.items():
+            assert np.array_equal(v, to_np(again[k])), k
+    L.svt_release_graphs()
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_tiny_random_streams(bank, seed):
+    """Ragged tiny inputs: zero-combination roads, extreme constants and coordinates, cuts."""
+    rng = np.random.default_rng(1000 + seed)
+    ev = random_events(rng, n_events=int(rng.integers(1, 6)), max_roads=6,
+                       max_hits=int(rng.integers(1, 9)), min_hits=0 if seed % 3 == 0 else 1)
+    words = stream(ev)
+    f, q = random_bank(rng, extreme=(seed % 2 == 0))
+    cfg = oracle.make_config(chi2_cut=int(rng.choice([0, 10**6, 2**40, 2**62])),
+                             shift=int(rng.choice([10, 1, 7, 16, 30])))
+    ref = oracle.run(words, f, q, cfg)
+    compare(ref, run_plain(words, f, q, cfg), PLAIN_KEYS, f"plain tiny {seed}")
+    got, _ = run_batch(words, f, q, cfg, ref=ref, tune=TUNES[seed % len(TUNES)], graph=False)
+    compare(ref, got, BATCH_KEYS, f"batch tiny {seed}")
+
+
+@pytest.mark.parametrize("extreme", [False, True])
+def test_giant_roads_span_many_tiles(bank, extreme):
+    """Roads of 8^5 = 32768 combinations cut by several 4096-combination tiles.
+
+    With extreme constants and a cut above 2^49 every combination is accepted with a chi2 too
+    large for the packed best-track key, which exercises the exact rescan and the merge of
+    per-tile partial results."""
+    rng = np.random.default_rng(7)
+    events = []
+    for e in range(3):
+        roads = []
+        for r in range(3):
+            hits = [(l, int(rng.integers(-4096, 4096))) for l in range(5) for _ in range(8)]
+            if r == 1:  # embed a noise-free track so the road has an accepted best
+                s = 10 + r
+                x = bank.A[s] @ np.array([5, -6, 7]) + bank.b[s]
+                hits[8 * 4 + 3] = (4, int(x[4]))
+                for l in range(4):
+                    hits[8 * l + 5] = (l, int(x[l]))
+            roads.append((10 + r, [hits[i] for i in rng.permutation(len(hits))]))
+        events.append(roads)
+    words = stream(events)
+    f, q, cfg = bank.f, bank.q, CFG
+    if extreme:
+        f, q = random_bank(np.random.default_rng(8), extreme=True)
+        cfg = oracle.make_config(chi2_cut=2**62, shift=3)
+    ref = oracle.run(words, f, q, cfg)
+    assert ref["n_combos"] == 9 * 32768
+    if extreme:
+        assert int(np.asarray(ref["best_chi2"]).min()) > 2**49
+    for t in TUNES:
+        got, _ = run_batch(words, f, q, cfg, ref=ref, tune=t, graph=False)
+        compare(ref, got, BATCH_KEYS, f"giant extreme={extreme}")
+    compare(ref, run_plain(words, f, q, cfg), PLAIN_KEYS, f"giant plain extreme={extreme}")
+
+
+def test_empty_input(bank):
+    words = np.zeros(0, np.uint32)
+    got, _ = run_batch(words, bank.f, bank.q, CFG, ref=dict(n_roads=0, n_combos=0), graph=False)
+    assert got["n_roads"] == 0 and got["n_combos"] == 0 and got["n_kept"] == 0
+    r = run_plain(words, bank.f, bank.q, CFG)
+    assert r["n_roads"] == 0 and r["n_combos"] == 0
+
+
+def test_split_at_event_boundaries(samples, bank):
+    """Results of a batch cut at an event boundary equal the whole batch's."""
+    s, ref = samples["c2"]
+    cut = 1234
+    w1, w2 = s.event_slice(0, cut), s.event_slice(cut, s.n_events)
+    r1, _ = run_batch(w1, bank.f, bank.q, CFG, graph=False)
+    r2, _ = run_batch(w2, bank.f, bank.q, CFG, graph=False)
+    for k in ["p0", "p1", "p2", "chi2", "accept"]:
+        both = np.concatenate([to_np(r1[k]), to_np(r2[k])])
+        assert np.array_equal(both, np.asarray(ref[k])), k
+    for k, kk in [("best_k", "best_k"), ("best_chi2", "best_chi2"), ("best_nacc", "best_n_accept")]:
+        both = np.concatenate([to_np(r1[kk]), to_np(r2[kk])])
+        assert np.array_equal(both, np.asarray(ref[k])), k
+
+
+def test_graph_replay_with_new_batches(bank):
+    """One captured graph serves batches of different sizes loaded into the same buffers."""
+    big = synth.make_sample("c4", n_events=64, bank=bank)
+    ref_big = oracle.run(big.words, bank.f, bank.q, CFG)
+    wc, rc, cc = len(big.words), ref_big["n_roads"] + 1, ref_big["n_combos"] + 4
+    runner = P.BatchRunner(gpu_cfg(CFG), P.device_bank(bank.f, bank.q), wc, rc, cc, kept_cap=cc,
+                           graph=True)
+    for e0, e1 in [(0, 64), (3, 10), (10, 11), (0, 40), (20, 64)]:
+        words = big.event_slice(e0, e1)
+        ref = oracle.run(words, bank.f, bank.q, CFG)
+        got, _ = run_batch(words, bank.f, bank.q, CFG, runner=runner)
+        compare(ref, got, BATCH_KEYS, f"replay {e0}-{e1}")
+    L.svt_release_graphs()
+
+
+def _err_of(got_runner):
+    return got_runner.error()
+
+
+def test_input_errors_are_reported(bank):
+    good = [[(1, [(l, 5) for l in range(5)]), (2, [(l, 6) for l in range(5)])]]
+    words = stream(good)
+    bad_layer = words.copy()
+    bad_layer[7] = pack(5, 6, 2, 0)
+    too_many = stream([[(1, [(l, 5) for l in range(5)]), (2, [(0, 1)] * 9 + [(l, 1) for l in range(1, 5)])]])
+    cases = [(bad_layer, CFG, L.SVT_ERR_LAYER, 7), (too_many, CFG, L.SVT_ERR_HITS, 1),
+             (words, oracle.make_config(n_sets=2), L.SVT_ERR_SET, 1)]
+    for w, cfg, status, index in cases:
+        st, *_ , ei = oracle.count(w, cfg)
+        assert (st, ei) == (status, index)
+        runner = P.BatchRunner(gpu_cfg(cfg), P.device_bank(bank.f, bank.q), 64, 64, 4096,
+                               kept_cap=64, graph=False)
+        runner.load(P.words_tensor(w)).run()
+        torch.cuda.synchronize()
+        assert runner.error() == (status, index)
+        with pytest.raises(P.DeviceError):
+            run_plain(w, bank.f, bank.q, cfg)
+
+
+def test_capacity_errors_report_required_sizes(samples, bank):
+    s, ref = samples["c1"]
+    w = P.words_tensor(s.words)
+    dbank = P.device_bank(bank.f, bank.q)
+    nr, nc, nk = ref["n_roads"], ref["n_combos"], ref["n_kept"]
+    for caps, which in [((nr - 1, nc, nk), 0), ((nr, nc - 1, nk), 1), ((nr, nc, nk - 1), 2)]:
+        runner = P.BatchRunner(gpu_cfg(CFG), dbank, len(s.words), caps[0], caps[1],
+                               kept_cap=caps[2], graph=False)
+        runner.load(w).run()
+        torch.cuda.synchronize()
+        assert runner.error() == (L.SVT_ERR_CAPACITY, which)
+        sz = runner.sizes()
+        assert sz["n_roads"] == nr
+        if which >= 1:
+            assert sz["n_combos"] == nc
+        if which == 2:
+            assert sz["n_kept"] == nk
+    # retry with the reported sizes succeeds
+    runner = P.BatchRunner(gpu_cfg(CFG), dbank, len(s.words), nr, nc, kept_cap=nk, graph=False)
+    runner.load(w).run()
+    compare(ref, runner.result(), BATCH_KEYS, "retry")
+
+
+def test_words_capacity_of_device_count(bank):
+    """A device word count above word_cap is an error, never an out-of-bounds read."""
+    s = synth.make_sample("c1", n_events=4, bank=bank)
+    runner = P.BatchRunner(gpu_cfg(CFG), P.device_bank(bank.f, bank.q), len(s.words), 64, 4096,
+                           graph=False)
+    runner.load(P.words_tensor(s.words))
+    runner.d_n[0].fill_(len(s.words) + 100)
+    runner.run()
+    torch.cuda.synchronize()
+    assert runner.error() == (L.SVT_ERR_CAPACITY, 3)
+
+
+def test_noise_free_tracks_on_gpu(samples, bank):
+    s, ref = samples["c2"]
+    got, _ = run_batch(s.words, bank.f, bank.q, CFG, ref=ref, graph=False)
+    cb = to_np(got["road_combo_begin"])
+    tr = np.nonzero(s.true_road)[0]
+    for r in tr[:2000]:
+        k = 0
+        for l in range(5):
+            k = k * int(s.road_nhits[r, l]) + int(s.true_slot[r, l])
+        g = cb[r] + k
+        assert (int(got["p0"][g]), int(got["p1"][g]), int(got["p2"][g])) == tuple(s.true_t[r])
+        assert int(got["chi2"][g]) == 0
