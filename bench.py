@@ -34,6 +34,79 @@ def algorithmic_bytes(n_combos, n_words, n_roads):
     return 21 * n_combos + 4 * n_words + 28 * n_roads
 
 
+def fused_kernel_ms(runner, steps, warmup):
+    """Average duration of the fused kernel alone: HIP events recorded on the runner's stream
+    right before and after its launch (direct launches, same launch configuration)."""
+    import numpy as np
+    import torch
+    from paper_1312_0917_amd import _lib as L
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(runner.stream)
+    ev1.record(runner.stream)
+    torch.cuda.synchronize()
+    L.svt_set_fused_timing_events(ev0, ev1)
+    graph = runner.graph
+    runner.graph = False
+    kms = []
+    try:
+        for i in range(warmup + steps):
+            runner.run()
+            ev1.synchronize()
+            if i >= warmup:
+                kms.append(ev0.elapsed_time(ev1))
+    finally:
+        L.svt_set_fused_timing_events(None, None)
+        runner.graph = graph
+    return float(np.mean(kms))
+
+
+def measure_large(config, n_events, passes, tune, bank):
+    """Max-scale run: whole batch resident in HBM, graph replays, fused-kernel roofline."""
+    import torch
+
+    import oracle
+    from paper_1312_0917_amd import _lib as L
+    from paper_1312_0917_amd import pipeline as P
+    from paper_1312_0917_amd import synth
+
+    log(f"generating {config} ({n_events} events)")
+    sample = synth.make_sample(config, bank=bank, n_events=n_events, workers=16)
+    cut = synth.config_chi2_cut(config)
+    n_words, n_roads = len(sample.words), sample.n_roads
+    n_combos = sample.expected_combos()
+    runner = P.BatchRunner(L.make_config(chi2_cut=cut), P.device_bank(bank.f, bank.q), n_words,
+                           n_roads, n_combos, kept_cap=0, tune=tune, graph=True, with_c=False)
+    runner.load(P.words_tensor(sample.words))
+    del sample
+    runner.run()
+    torch.cuda.synchronize()
+    sz = runner.sizes()
+    assert sz["n_combos"] == n_combos and runner.error()[0] == 0, (sz, runner.error())
+    log(f"{config}: {passes} timed passes over {n_combos} combinations")
+    t0 = time.perf_counter()
+    for _ in range(passes):
+        runner.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / passes
+    k_ms = fused_kernel_ms(runner, passes, 1)
+    L.svt_release_graphs()
+    alg = algorithmic_bytes(n_combos, n_words, n_roads)
+    ach = alg / (k_ms * 1e-3) / 1e9
+    out = dict(workload=f"{config}: {n_events} events, {n_roads} roads, {n_words} hit words, "
+                        f"{n_combos} combinations",
+               value=n_combos / dt, unit="fitted combinations/s", ms_per_pass=round(dt * 1e3, 4),
+               passes=passes,
+               roofline=dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                             frac=round(ach / HBM_PEAK_GBS, 4), kernel="k_fused",
+                             kernel_ms=round(k_ms, 4), algorithmic_bytes=alg,
+                             bytes_per_combination=round(alg / n_combos, 3)))
+    del runner
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_cpu_baseline(sample, bank, cfg, seconds):
     import oracle
 
@@ -56,6 +129,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--occ", type=int, default=0)
+    ap.add_argument("--large-events", type=int, default=10000,
+                    help="events of the max-scale run (10000 x 2048 roads); 0 skips it")
+    ap.add_argument("--large-passes", type=int, default=5)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -112,22 +188,7 @@ def main():
 
     # ---- fused kernel alone: HIP events on the runner's stream around each launch ---------
     log("fused kernel timing")
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(runner.stream)
-    ev1.record(runner.stream)
-    torch.cuda.synchronize()
-    L.svt_set_fused_timing_events(ev0, ev1)
-    runner.graph = False
-    kms = []
-    for i in range(W + K):
-        runner.run()
-        ev1.synchronize()
-        if i >= W:
-            kms.append(ev0.elapsed_time(ev1))
-    L.svt_set_fused_timing_events(None, None)
-    runner.graph = True
-    k_ms = float(np.mean(kms))
+    k_ms = fused_kernel_ms(runner, K, W)
     alg = algorithmic_bytes(n_combos, n_words, n_roads)
     achieved = alg / (k_ms * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -157,12 +218,19 @@ def main():
                      batched_over_plain=round(plain_s / batch_s, 2))
         del pr
 
+    large = None
+    if args.large_events > 0:
+        L.svt_release_graphs()
+        del runner
+        torch.cuda.empty_cache()
+        large = measure_large("c5", args.large_events, args.large_passes, tune, bank)
+
     cpu = None
     if not args.no_cpu:
         log(f"cpu oracle baseline (~{args.cpu_seconds:.0f} s)")
         cpu = run_cpu_baseline(sample, bank, cfg, args.cpu_seconds)
 
-    t = runner.tune
+    t = tune
     out = dict(
         metric=METRIC, value=value, unit="fitted combinations/s", n_gpus=1, steps=K, warmup=W,
         ms_per_step=round(batch_s * 1e3, 5), higher_is_better=True, scaling="weak",
@@ -175,7 +243,7 @@ def main():
                     tune=dict(tile_combos=t.tile_combos, chunk_roads=t.chunk_roads,
                               wg_size=t.wg_size, wgs_per_cu=t.wgs_per_cu),
                     device=dev_name),
-        roofline=roofline, cpu_baseline=cpu, plain=plain)
+        roofline=roofline, cpu_baseline=cpu, plain=plain, max_scale=large)
     print(json.dumps(out), flush=True)
 
 

@@ -62,6 +62,7 @@ struct BatchWs {
     int64_t tiles_cap;
     int64_t *kb;
     int64_t kbn;
+    int16_t *coords;
 };
 BatchWs carve_batch(Carver &c, int64_t word_cap, int64_t road_cap, int64_t combo_cap,
                     int64_t tile) {
@@ -77,11 +78,12 @@ BatchWs carve_batch(Carver &c, int64_t word_cap, int64_t road_cap, int64_t combo
     w.part = c.take<Partial>(2 * w.tiles_cap);
     w.kbn = ceil_div(combo_cap > 0 ? combo_cap : 1, kKeptBlock);
     w.kb = c.take<int64_t>(w.kbn);
+    w.coords = c.take<int16_t>(word_cap);
     return w;
 }
 
 svt_tune resolve_tune(const svt_tune *t) {
-    svt_tune r{8192, 64, 256, 4};
+    svt_tune r{4096, 128, 256, 4};
     if (t) {
         if (t->tile_combos) r.tile_combos = t->tile_combos;
         if (t->chunk_roads) r.chunk_roads = t->chunk_roads;
@@ -297,8 +299,8 @@ static svt_status batch_sequence(const FusedLaunch &f, const BatchWs &w, int64_t
     SVT_TRY(launch_scan(w.wb, w.nb, 2, nw, kSegBlockWords, const_cast<int64_t *>(f.d_n_roads),
                         w.scalars, road_cap, 0, err, false, stream));
     SVT_TRY(launch_seg_emit(f.words, nw, w.nb, w.wb, f.roads, road_cap, err, stream));
-    SVT_TRY(launch_road_fill(f.words, nw, f.d_n_roads, road_cap, f.roads, f.cfg, nullptr,
-                             nullptr, err, stream));
+    SVT_TRY(launch_road_fill(f.words, nw, f.d_n_roads, road_cap, f.roads, f.cfg,
+                             const_cast<int16_t *>(f.coords), nullptr, err, stream));
     SVT_TRY(launch_combo_count(f.roads, nr, w.rbn, w.rb, err, stream));
     SVT_TRY(launch_scan(w.rb, 0, 1, nr, kRoadBlock, const_cast<int64_t *>(f.d_n_combos), nullptr,
                         combo_cap, 1, err, true, stream));
@@ -355,6 +357,7 @@ svt_status svt_process_batch(const svt_fconst *bank, const svt_config *cfg, cons
     f.tune = t;
     f.words = words;
     f.d_n_words = d_n_words;
+    f.coords = w.coords;
     f.roads = *roads;
     f.d_n_roads = d_n_roads;
     f.d_n_combos = d_n_combos;

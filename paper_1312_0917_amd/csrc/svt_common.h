@@ -182,6 +182,7 @@ struct FusedLaunch {
     svt_tune tune;
     const uint32_t *words;
     const int64_t *d_n_words;
+    const int16_t *coords;     // workspace: coordinates grouped by layer inside each road
     svt_roads roads;
     const int64_t *d_n_roads;
     const int64_t *d_n_combos;

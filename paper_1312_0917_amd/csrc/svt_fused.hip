@@ -1,17 +1,19 @@
 // Persistent fused combine + fit + select kernel of libsvt, and its split-road fixup.
 //
 // The fit of section II is p_j = sum_l f[j][l] x_l + q_j followed by the fixed-point shift.
-// Because the sum is linear in the hits, each hit's contribution f[j][l] * x_l (six int32 per
-// hit, the "partial-product vector") is computed once per road and staged in LDS; every
-// combination then costs five LDS vector reads and integer adds instead of thirty multiplies.
-// The offset is split exactly as q = qh * 2^s + ql with 0 <= ql < 2^s: ql is folded into the
-// layer-0 vectors, so the five-term sum stays inside int32, and
+// Constants are int16 and coordinates int13, so the five products of one parameter are three
+// packed 16-bit dot products (v_dot2_i32_i16) once the coordinates of layers (0,1) and (2,3)
+// are paired: each road's hits are staged in LDS as small tables of coordinate pairs, and one
+// combination is three LDS reads plus eighteen dot products.  The offset is split exactly as
+// q = qh * 2^s + ql with 0 <= ql < 2^s: ql seeds the accumulator, so the sum stays inside
+// int32, and
 //     floor((S + q) / 2^s) = qh + floor((S + ql) / 2^s)       (exact for every integer S).
 //
 // Work distribution: combinations are numbered globally (road-major, combo_begin from the
 // pre-pass); workgroups of a persistent grid take tiles of tile_combos consecutive
 // combinations from an atomic counter.  A tile stages its roads in LDS in chunks of up to
-// CHUNK roads (bounded by the LDS hit capacity), and each lane fits 4 consecutive
+// CHUNK roads (bounded by the LDS word and table capacities): the chunk's hit words are one
+// contiguous span of the input, copied with coalesced loads.  Each lane fits 4 consecutive
 // combinations so that every record array is written with 16-byte coalesced stores.  Roads
 // entirely inside a tile get their best track from LDS atomics; roads cut by tile boundaries
 // leave partial (key, count) pairs per tile that the fixup kernel merges.
@@ -20,8 +22,9 @@
 namespace svt {
 namespace {
 
-constexpr int kHitCap = 1024;          // hits staged per chunk (a road has at most 5 * 8 = 40)
-constexpr int kMaxKb = 16;             // kept-count blocks per tile (tile_combos <= 65536)
+constexpr int kWordCap = 2048;         // hit words staged per chunk (a road has at most 40)
+constexpr int kTabCap = 2048;          // coordinate-pair table entries per chunk (<= 136 per road)
+constexpr int kMaxKb = 4;              // kept-count blocks per tile (tile_combos <= 16384)
 constexpr uint32_t kKMask = (1u << kKeyKBits) - 1;
 
 struct FArgs {
@@ -29,7 +32,7 @@ struct FArgs {
     int32_t shift;
     int32_t n_sets;
     int64_t cut;
-    const uint32_t *words;
+    const int16_t *coords;  // hit coordinates grouped by layer inside each road
     svt_roads roads;
     const int64_t *d_n_roads;
     const int64_t *d_n_combos;
@@ -47,19 +50,38 @@ struct FArgs {
     int64_t combo_cap;
 };
 
-// Per-road data of the current chunk, in LDS (96 bytes).
+// Per-road indexing data of the current chunk, in LDS (32 bytes).
 struct alignas(16) RoadMeta {
-    int32_t C;         // combinations
-    uint32_t nh;       // packed hits per layer
-    uint32_t mg[4];    // division magics for n1..n4 (0 when n == 1)
-    int32_t base[5];   // LDS vector index of the first hit of each layer
-    int32_t qh[6];     // offsets >> shift
-    int32_t pad[7];
+    int32_t C;      // combinations
+    uint32_t m4;    // division magic of n4 (0 when n4 == 1)
+    uint32_t m23;   // division magic of n2 * n3 (0 when 1)
+    uint32_t nn;    // n4 | (n2 * n3) << 8
+    int32_t b01;    // table index of the (h0, h1) coordinate pairs
+    int32_t b23;    // table index of the (h2, h3) pairs
+    int32_t b4;     // table index of the layer-4 coordinates
+    int32_t wo;     // first staged word of the road
 };
-static_assert(sizeof(RoadMeta) == 96, "RoadMeta layout");
 
-// floor(k / n) for 0 <= k < 2^15 and 1 <= n <= 8 with m = ceil(2^32 / n) (m = 0 for n = 1):
-// k * (m * n - 2^32) < 2^15 * 8 < 2^32, so the high word of k * m is exact.
+// Per-road constants of the current chunk, packed for the dot products (128 bytes).
+struct alignas(16) RoadConst {
+    int32_t F01[6];  // (f[j][0], f[j][1]) as an int16 pair
+    int32_t F23[6];  // (f[j][2], f[j][3])
+    int32_t F4[6];   // (f[j][4], 0)
+    int32_t ql[6];   // q[j] mod 2^shift
+    int32_t qh[6];   // floor(q[j] / 2^shift)
+    int32_t pad[2];
+};
+
+typedef short v2s __attribute__((ext_vector_type(2)));
+
+// a.lo * b.lo + a.hi * b.hi + c on signed 16-bit halves (v_dot2_i32_i16, no clamping).
+__device__ __forceinline__ int32_t dot2(int32_t a, int32_t b, int32_t c) {
+    return __builtin_amdgcn_sdot2(__builtin_bit_cast(v2s, a), __builtin_bit_cast(v2s, b), c,
+                                  false);
+}
+
+// floor(k / n) for 0 <= k < 2^15 and 1 <= n <= 64 with m = ceil(2^32 / n) (m = 0 for n = 1):
+// k * (m * n - 2^32) < 2^15 * 64 < 2^32, so the high word of k * m is exact.
 __device__ __forceinline__ uint32_t div_small(uint32_t k, uint32_t m) {
     return m ? __umulhi(k, m) : k;
 }
@@ -68,50 +90,67 @@ __host__ __device__ constexpr uint32_t magic_of(uint32_t n) {
     return n <= 1 ? 0u : static_cast<uint32_t>((0x100000000ull + n - 1) / n);
 }
 
+__device__ __forceinline__ int32_t pack16(int32_t lo, int32_t hi) {
+    return static_cast<int32_t>((static_cast<uint32_t>(lo) & 0xFFFFu) |
+                                (static_cast<uint32_t>(hi) << 16));
+}
+
 struct Fit {
     int32_t v[6];
     int64_t chi2;
 };
 
-// Fit combination k of the road described by m, from the partial-product vectors P.
-__device__ __forceinline__ Fit fit_combo(const RoadMeta &m, uint32_t k, const int2 *P,
-                                         int32_t shift) {
-    uint32_t h[5];
-    uint32_t rest = k;
-#pragma unroll
-    for (int l = 4; l >= 1; --l) {
-        const uint32_t n = nh_of(m.nh, l);
-        const uint32_t q = div_small(rest, m.mg[l - 1]);
-        h[l] = rest - q * n;
-        rest = q;
-    }
-    h[0] = rest;
-    int32_t a[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-    for (int l = 0; l < 5; ++l) {
-        const int2 *v = P + 3 * (m.base[l] + static_cast<int32_t>(h[l]));
-        const int2 x0 = v[0], x1 = v[1], x2 = v[2];
-        a[0] += x0.x; a[1] += x0.y; a[2] += x1.x; a[3] += x1.y; a[4] += x2.x; a[5] += x2.y;
-    }
+// Fit combination k of a road.  k = (i01 * n23 + i23) * n4 + h4, where i01 = h0 * n1 + h1
+// and i23 = h2 * n3 + h3 index the coordinate-pair tables.  Each sum
+//     ql_j + f_j0 x0 + f_j1 x1 + f_j2 x2 + f_j3 x3 + f_j4 x4
+// is three packed 16-bit dot products; |sum| < 2^30 + 5 * 2^27 < 2^31, so int32 is exact.
+__device__ __forceinline__ Fit fit_combo(const RoadMeta &m, const RoadConst &c, uint32_t k,
+                                         const int32_t *XT, int32_t shift) {
+    const uint32_t n4 = m.nn & 0xFFu, n23 = m.nn >> 8;
+    const uint32_t q4 = div_small(k, m.m4);
+    const uint32_t h4 = k - q4 * n4;
+    const uint32_t i01 = div_small(q4, m.m23);
+    const uint32_t i23 = q4 - i01 * n23;
+    const int32_t x01 = XT[m.b01 + static_cast<int32_t>(i01)];
+    const int32_t x23 = XT[m.b23 + static_cast<int32_t>(i23)];
+    const int32_t x4 = XT[m.b4 + static_cast<int32_t>(h4)];
     Fit f;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) f.v[j] = (a[j] >> shift) + m.qh[j];
+    for (int j = 0; j < 6; ++j) {
+        int32_t acc = dot2(c.F01[j], x01, c.ql[j]);
+        acc = dot2(c.F23[j], x23, acc);
+        acc = dot2(c.F4[j], x4, acc);
+        f.v[j] = (acc >> shift) + c.qh[j];
+    }
     f.chi2 = static_cast<int64_t>(f.v[3]) * f.v[3] + static_cast<int64_t>(f.v[4]) * f.v[4] +
              static_cast<int64_t>(f.v[5]) * f.v[5];
     return f;
 }
 
+// int16 element i of a constant set's f[6][5] read as 8-byte words
+__device__ __forceinline__ int32_t f_at(const uint2 *fw, int i) {
+    const uint2 w = fw[i >> 2];
+    const uint32_t d = ((i >> 1) & 1) ? w.y : w.x;
+    return static_cast<int32_t>(static_cast<int16_t>((i & 1) ? (d >> 16) : (d & 0xFFFFu)));
+}
+
 template <int WG, int CHUNK>
 __global__ __launch_bounds__(WG) void k_fused(FArgs a) {
-    static_assert(CHUNK <= kWaveSize, "chunk roads are staged by one wave");
-    __shared__ int2 P[3 * kHitCap];           // 6 int32 per staged hit
+    static_assert(CHUNK <= WG && CHUNK <= 256, "one thread per staged road, road index in a byte");
+    constexpr int kMapCap = kKeptBlock * kMaxKb / 4;  // groups of 4 combinations in a tile
+    constexpr int kCopy = (kWordCap + WG - 1) / WG;
+    __shared__ int16_t G[kWordCap];           // layer-grouped coordinates of the staged roads
+    __shared__ int32_t XT[kTabCap];           // coordinate-pair tables
+    __shared__ uint8_t M[kMapCap];            // group of 4 combinations -> staged road
     __shared__ RoadMeta meta[CHUNK];
-    __shared__ int32_t s_rb[CHUNK + 1];       // road begin relative to the tile start
+    __shared__ RoadConst rcst[CHUNK];
+    __shared__ int32_t s_rb[CHUNK];           // road begin relative to the tile start
     __shared__ unsigned long long s_key[CHUNK];
     __shared__ uint32_t s_nacc[CHUNK];
     __shared__ uint32_t s_kb[kMaxKb];
-    __shared__ int64_t s_tile;
-    __shared__ int32_t s_nr;
+    __shared__ int64_t s_scan[WG / kWaveSize + 1];
+    __shared__ int64_t s_tile, s_first, s_span;
+    __shared__ int32_t s_nr, s_nwords;
 
     if (has_error(a.err)) return;
     const int64_t n_roads = *a.d_n_roads;
@@ -121,148 +160,219 @@ __global__ __launch_bounds__(WG) void k_fused(FArgs a) {
     const int64_t n_tiles = (n_combos + T - 1) / T;
     if (n_tiles > a.tiles_cap) return;
     const int tid = threadIdx.x;
-    const int wave = tid / kWaveSize;
-    const int lane = tid % kWaveSize;
     const uint32_t qlmask = (1u << a.shift) - 1u;
 
-    while (true) {
-        if (tid == 0) s_tile = static_cast<int64_t>(atomicAdd(a.tile_counter, 1u));
+    int64_t t = blockIdx.x;  // first tile by block index, the rest from the counter
+    int64_t r_first = t < n_tiles ? a.tile_first_road[t] : 0;
+    while (t < n_tiles) {
+        uint32_t ticket = 0;
+        if (tid == 0) ticket = atomicAdd(a.tile_counter, 1u);  // next tile, fetched early
         if (tid < kMaxKb) s_kb[tid] = 0;
-        __syncthreads();
-        const int64_t t = s_tile;
-        if (t >= n_tiles) break;
         const int64_t tile_start = t * T;
         const int64_t tile_end = (tile_start + T < n_combos) ? tile_start + T : n_combos;
         const int32_t tile_len = static_cast<int32_t>(tile_end - tile_start);
-        int64_t r_next = a.tile_first_road[t];
+        int64_t r_next = r_first;
+        int64_t next_first = 0;
+        bool prefetched = false;
 
         while (true) {
-            // ---- phase A (wave 0): chunk road table, hit grouping, partial-product vectors
-            if (wave == 0) {
-                const int64_t r = r_next + lane;
-                bool valid = false;
-                int64_t cb = 0, hb = 0;
-                int32_t C = 0, s = 0;
-                uint32_t nh = 0;
-                if (lane < CHUNK && r < n_roads) {
-                    cb = a.roads.combo_begin[r];
-                    valid = cb < tile_end;
-                    if (valid) {
-                        C = a.roads.ncombo[r];
-                        nh = a.roads.nhits[r];
-                        hb = a.roads.hit_begin[r];
-                        s = a.roads.set[r];
-                    }
+            // ---- A1: one thread per candidate road: sizes, capacity, indexing, constants
+            const int64_t r = r_next + tid;
+            bool valid = false;
+            int64_t cb = 0, hb = 0;
+            int32_t C = 0, s = 0;
+            uint32_t nh = 0;
+            if (tid < CHUNK && r < n_roads) {
+                cb = a.roads.combo_begin[r];
+                valid = cb < tile_end;
+                if (valid) {
+                    C = a.roads.ncombo[r];
+                    nh = a.roads.nhits[r];
+                    hb = a.roads.hit_begin[r];
+                    s = a.roads.set[r];
                 }
-                int32_t nhit = 0;
-                if (valid && C > 0)
-                    for (int l = 0; l < 5; ++l) nhit += static_cast<int32_t>(nh_of(nh, l));
-                const int32_t incl = wave_incl_scan(nhit);
-                const bool fits = valid && incl <= kHitCap;
-                const int nr = __popcll(__ballot(fits));
-                if (lane < nr) {
-                    RoadMeta m;
-                    m.C = C;
-                    m.nh = nh;
-                    int32_t base = incl - nhit;
+            }
+            const int32_t n0 = nh_of(nh, 0), n1 = nh_of(nh, 1), n2 = nh_of(nh, 2),
+                          n3 = nh_of(nh, 3), n4 = nh_of(nh, 4);
+            const int32_t nwords = n0 + n1 + n2 + n3 + n4;
+            const int32_t ntab = (valid && C > 0) ? n0 * n1 + n2 * n3 + n4 : 0;
+            const int64_t packed = static_cast<int64_t>(valid ? nwords : 0) |
+                                   (static_cast<int64_t>(ntab) << 32);
+            if (tid == 0) {
+                s_nr = 0;
+                s_nwords = 0;
+            }
+            int64_t total;
+            const int64_t ex = block_excl_scan<int64_t, WG>(packed, s_scan, total);
+            const int32_t wo = static_cast<int32_t>(ex & 0xFFFFFFFF);
+            const int32_t to = static_cast<int32_t>(ex >> 32);
+            const bool fits = valid && wo + nwords <= kWordCap && to + ntab <= kTabCap;
+            if (fits) {
+                atomicMax(&s_nr, tid + 1);
+                atomicMax(&s_nwords, wo + nwords);
+                RoadMeta m;
+                m.C = C;
+                m.m4 = magic_of(n4);
+                m.m23 = magic_of(n2 * n3);
+                m.nn = static_cast<uint32_t>(n4) | (static_cast<uint32_t>(n2 * n3) << 8);
+                m.b01 = to;
+                m.b23 = to + n0 * n1;
+                m.b4 = to + n0 * n1 + n2 * n3;
+                m.wo = wo;
+                meta[tid] = m;
+                s_rb[tid] = static_cast<int32_t>(cb - tile_start);
+                s_key[tid] = ~0ull;
+                s_nacc[tid] = 0;
+                if (tid == 0) s_span = hb;
+                // constant set: f[6][5] int16 (60 bytes), 4 bytes pad, q[6] int32
+                const uint2 *fw = reinterpret_cast<const uint2 *>(a.bank + s);
+                RoadConst rc;
 #pragma unroll
-                    for (int l = 0; l < 5; ++l) {
-                        m.base[l] = base;
-                        base += static_cast<int32_t>(nh_of(nh, l));
-                    }
-#pragma unroll
-                    for (int l = 1; l < 5; ++l) m.mg[l - 1] = magic_of(nh_of(nh, l));
-                    const svt_fconst *F = a.bank + s;
-                    int32_t ql[6];
-#pragma unroll
-                    for (int j = 0; j < 6; ++j) {
-                        const int32_t q = F->q[j];
-                        m.qh[j] = q >> a.shift;
-                        ql[j] = static_cast<int32_t>(static_cast<uint32_t>(q) & qlmask);
-                    }
-                    meta[lane] = m;
-                    s_rb[lane] = static_cast<int32_t>(cb - tile_start);
-                    s_key[lane] = ~0ull;
-                    s_nacc[lane] = 0;
-                    // group the road's hits by layer (stream order kept) and stage f.x
-                    uint64_t seen = 0;  // 8 bits per layer (5 layers: 40 bits)
-                    for (int32_t i = 0; i < nhit; ++i) {
-                        const uint32_t w = a.words[hb + i];
-                        const uint32_t l = w_layer(w);
-                        if (l >= 5) continue;  // excluded by the layer check of the pre-pass
-                        const int32_t x = w_coord(w);
-                        int32_t pos = 0;
-#pragma unroll
-                        for (int ll = 0; ll < 5; ++ll)
-                            if (static_cast<uint32_t>(ll) == l) pos = m.base[ll];
-                        pos += static_cast<int32_t>((seen >> (8 * l)) & 0xFF);
-                        seen += 1ull << (8 * l);
-                        if (pos >= kHitCap) continue;
-                        const int16_t *fc = &F->f[0][0] + l;  // column l: stride 5
-                        int32_t v[6];
-#pragma unroll
-                        for (int j = 0; j < 6; ++j)
-                            v[j] = static_cast<int32_t>(fc[5 * j]) * x + (l == 0 ? ql[j] : 0);
-                        int2 *dst = P + 3 * pos;
-                        dst[0] = make_int2(v[0], v[1]);
-                        dst[1] = make_int2(v[2], v[3]);
-                        dst[2] = make_int2(v[4], v[5]);
-                    }
+                for (int j = 0; j < 6; ++j) {
+                    rc.F01[j] = pack16(f_at(fw, 5 * j + 0), f_at(fw, 5 * j + 1));
+                    rc.F23[j] = pack16(f_at(fw, 5 * j + 2), f_at(fw, 5 * j + 3));
+                    rc.F4[j] = pack16(f_at(fw, 5 * j + 4), 0);
+                    const int32_t q = a.bank[s].q[j];
+                    rc.qh[j] = q >> a.shift;
+                    rc.ql[j] = static_cast<int32_t>(static_cast<uint32_t>(q) & qlmask);
                 }
-                if (lane == 0) {
-                    s_nr = nr;
-                    // sentinel: end of the last staged road
-                    s_rb[nr] = 0x7FFFFFFF;
-                }
+                rc.pad[0] = rc.pad[1] = 0;
+                rcst[tid] = rc;
             }
             __syncthreads();
             const int nr = s_nr;
             if (nr == 0) break;
+            if (tid == 0 && !prefetched) {  // first road of the next tile, while this one runs
+                const int64_t nt = static_cast<int64_t>(gridDim.x) + ticket;
+                next_first = nt < n_tiles ? a.tile_first_road[nt] : 0;
+                prefetched = true;
+            }
 
-            // ---- phase B (all waves): fit every combination of the chunk inside the tile
+            // ---- A2: copy the chunk's grouped coordinates (one contiguous span) into LDS
+            {
+                const int32_t nw = s_nwords;
+                const int16_t *src = a.coords + s_span;
+                int16_t v[kCopy];
+#pragma unroll
+                for (int u = 0; u < kCopy; ++u) {
+                    const int i = tid + u * WG;
+                    v[u] = i < nw ? src[i] : static_cast<int16_t>(0);
+                }
+#pragma unroll
+                for (int u = 0; u < kCopy; ++u) {
+                    const int i = tid + u * WG;
+                    if (i < nw) G[i] = v[u];
+                }
+            }
             const int32_t first_rb = s_rb[0];
             const int32_t last_end = s_rb[nr - 1] + meta[nr - 1].C;
             const int32_t cs = first_rb > 0 ? first_rb : 0;
             const int32_t ce = last_end < tile_len ? last_end : tile_len;
             const int32_t g_lo = cs >> 2, g_hi = (ce + 3) >> 2;
+            __syncthreads();
+
+            // ---- A3: per road, coordinate-pair tables and the group -> road map
+            if (tid < nr) {
+                if (C > 0) {
+                    const int32_t off1 = wo + n0, off2 = off1 + n1, off3 = off2 + n2,
+                                  off4 = off3 + n3;
+                    const int32_t b01 = to, b23 = to + n0 * n1, b4 = b23 + n2 * n3;
+                    for (int32_t h0 = 0; h0 < n0; ++h0) {
+                        const int32_t x0 = G[wo + h0];
+                        for (int32_t h1 = 0; h1 < n1; ++h1)
+                            XT[b01 + h0 * n1 + h1] = pack16(x0, G[off1 + h1]);
+                    }
+                    for (int32_t h2 = 0; h2 < n2; ++h2) {
+                        const int32_t x2 = G[off2 + h2];
+                        for (int32_t h3 = 0; h3 < n3; ++h3)
+                            XT[b23 + h2 * n3 + h3] = pack16(x2, G[off3 + h3]);
+                    }
+                    for (int32_t h4 = 0; h4 < n4; ++h4) XT[b4 + h4] = pack16(G[off4 + h4], 0);
+                }
+                // groups whose first combination inside [cs, ce) belongs to this road
+                const int32_t rb = s_rb[tid];
+                int32_t glo = rb <= cs ? g_lo : (rb + 3) >> 2;
+                int32_t ghi = g_hi;
+                if (tid + 1 < nr) {
+                    const int32_t nb = s_rb[tid + 1];
+                    ghi = nb <= cs ? g_lo : (nb + 3) >> 2;
+                }
+                if (ghi > g_hi) ghi = g_hi;
+                for (int32_t g = glo; g < ghi; ++g) M[g - g_lo] = static_cast<uint8_t>(tid);
+            }
+            __syncthreads();
+
+            // ---- B: fit every combination of the chunk that lies inside the tile
             for (int32_t g = g_lo + tid; g < g_hi; g += WG) {
                 const int32_t rel0 = g << 2;
                 const int32_t first = rel0 > cs ? rel0 : cs;
-                // last staged road whose begin <= first
-                int ri = 0;
-#pragma unroll
-                for (int step = CHUNK / 2; step > 0; step >>= 1)
-                    if (ri + step < nr && s_rb[ri + step] <= first) ri += step;
+                const int32_t last = (rel0 + 3 < ce - 1) ? rel0 + 3 : ce - 1;
+                int ri = M[g - g_lo];
                 RoadMeta m = meta[ri];
-                int32_t k = first - s_rb[ri];
+                int32_t rbase = s_rb[ri];
+                uint32_t valid_bits = 0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    valid_bits |= (rel0 + e >= cs && rel0 + e < ce) ? (1u << e) : 0u;
                 int32_t vp0[4], vp1[4], vp2[4], vc0[4], vc1[4], vc2[4];
                 int64_t vchi[4];
-                uint32_t acc_bits = 0, valid_bits = 0;
+                int32_t kk[4];
+                int rr4[4];
+                if (last - rbase < m.C) {
+                    // common case: every valid combination of the group is in road ri; the
+                    // four fits are independent (invalid slots compute a dummy k = 0)
+                    const RoadConst c = rcst[ri];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int32_t rel = rel0 + e;
-                    vp0[e] = vp1[e] = vp2[e] = vc0[e] = vc1[e] = vc2[e] = 0;
-                    vchi[e] = 0;
-                    if (rel >= cs && rel < ce) {
-                        while (k >= m.C && ri + 1 < nr) {  // bounded: never past the chunk
-                            k -= m.C;
-                            ++ri;
-                            m = meta[ri];
-                        }
-                        const Fit f = fit_combo(m, static_cast<uint32_t>(k), P, a.shift);
+                    for (int e = 0; e < 4; ++e) {
+                        const int32_t k = (valid_bits >> e) & 1u ? rel0 + e - rbase : 0;
+                        const Fit f = fit_combo(m, c, static_cast<uint32_t>(k), XT, a.shift);
                         vp0[e] = f.v[0]; vp1[e] = f.v[1]; vp2[e] = f.v[2];
                         vc0[e] = f.v[3]; vc1[e] = f.v[4]; vc2[e] = f.v[5];
                         vchi[e] = f.chi2;
-                        valid_bits |= 1u << e;
-                        if (f.chi2 <= a.cut) {
-                            acc_bits |= 1u << e;
-                            const unsigned long long key =
-                                best_key(f.chi2, static_cast<uint32_t>(k));
-                            atomicMin(&s_key[ri], key);
-                            atomicAdd(&s_nacc[ri], 1u);
-                            atomicAdd(&s_kb[rel >> 12], 1u);
+                        kk[e] = k;
+                        rr4[e] = ri;
+                    }
+                } else {
+                    int32_t k = first - rbase;
+                    RoadConst c = rcst[ri];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        vp0[e] = vp1[e] = vp2[e] = vc0[e] = vc1[e] = vc2[e] = 0;
+                        vchi[e] = 0;
+                        kk[e] = 0;
+                        rr4[e] = ri;
+                        if ((valid_bits >> e) & 1u) {
+                            if (k >= m.C) {
+                                while (k >= m.C && ri + 1 < nr) {  // bounded by the chunk
+                                    k -= m.C;
+                                    ++ri;
+                                    m = meta[ri];
+                                }
+                                c = rcst[ri];
+                            }
+                            const Fit f = fit_combo(m, c, static_cast<uint32_t>(k), XT, a.shift);
+                            vp0[e] = f.v[0]; vp1[e] = f.v[1]; vp2[e] = f.v[2];
+                            vc0[e] = f.v[3]; vc1[e] = f.v[4]; vc2[e] = f.v[5];
+                            vchi[e] = f.chi2;
+                            kk[e] = k;
+                            rr4[e] = ri;
+                            ++k;
                         }
-                        ++k;
+                    }
+                }
+                uint32_t acc_bits = 0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    acc_bits |= ((valid_bits >> e) & 1u) && vchi[e] <= a.cut ? (1u << e) : 0u;
+                if (acc_bits) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if ((acc_bits >> e) & 1u) {
+                            atomicMin(&s_key[rr4[e]], static_cast<unsigned long long>(
+                                                          best_key(vchi[e], static_cast<uint32_t>(kk[e]))));
+                            atomicAdd(&s_nacc[rr4[e]], 1u);
+                            atomicAdd(&s_kb[(rel0 + e) >> 12], 1u);
+                        }
                     }
                 }
                 const int64_t gi = tile_start + rel0;
@@ -297,14 +407,15 @@ __global__ __launch_bounds__(WG) void k_fused(FArgs a) {
             }
             __syncthreads();
 
-            // ---- phase C (wave 0): best track of roads inside the tile, partials otherwise
-            if (wave == 0 && lane < nr) {
-                const RoadMeta m = meta[lane];
-                const int32_t rb = s_rb[lane];
-                const int64_t r = r_next + lane;
+            // ---- C: best track of roads inside the tile, exact partials otherwise
+            if (tid < nr) {
+                const RoadMeta m = meta[tid];
+                const RoadConst c = rcst[tid];
+                const int32_t rb = s_rb[tid];
+                const int64_t rr = r_next + tid;
                 if (m.C > 0) {
-                    const unsigned long long key = s_key[lane];
-                    const uint32_t nacc = s_nacc[lane];
+                    const unsigned long long key = s_key[tid];
+                    const uint32_t nacc = s_nacc[tid];
                     // this road's combinations inside the tile: k in [k_lo, k_hi)
                     const int32_t k_lo = rb < 0 ? -rb : 0;
                     const int32_t k_hi = (rb + m.C <= tile_len) ? m.C : tile_len - rb;
@@ -316,7 +427,7 @@ __global__ __launch_bounds__(WG) void k_fused(FArgs a) {
                         if (bchi == kKeyChiMax) {  // saturated key: exact rescan of the part
                             bchi = ~0ull;
                             for (int32_t k = k_lo; k < k_hi; ++k) {
-                                const Fit f = fit_combo(m, static_cast<uint32_t>(k), P, a.shift);
+                                const Fit f = fit_combo(m, c, static_cast<uint32_t>(k), XT, a.shift);
                                 if (f.chi2 <= a.cut && static_cast<uint64_t>(f.chi2) < bchi) {
                                     bchi = static_cast<uint64_t>(f.chi2);
                                     bk = static_cast<uint32_t>(k);
@@ -325,20 +436,20 @@ __global__ __launch_bounds__(WG) void k_fused(FArgs a) {
                         }
                     }
                     if (rb >= 0 && rb + m.C <= tile_len) {
-                        a.best.n_accept[r] = static_cast<int32_t>(nacc);
+                        a.best.n_accept[rr] = static_cast<int32_t>(nacc);
                         if (bchi == ~0ull) {
-                            a.best.k[r] = -1;
-                            a.best.p0[r] = INT32_MIN;
-                            a.best.p1[r] = INT32_MIN;
-                            a.best.p2[r] = INT32_MIN;
-                            a.best.chi2[r] = INT64_MAX;
+                            a.best.k[rr] = -1;
+                            a.best.p0[rr] = INT32_MIN;
+                            a.best.p1[rr] = INT32_MIN;
+                            a.best.p2[rr] = INT32_MIN;
+                            a.best.chi2[rr] = INT64_MAX;
                         } else {
-                            const Fit f = fit_combo(m, bk, P, a.shift);
-                            a.best.k[r] = static_cast<int32_t>(bk);
-                            a.best.p0[r] = f.v[0];
-                            a.best.p1[r] = f.v[1];
-                            a.best.p2[r] = f.v[2];
-                            a.best.chi2[r] = static_cast<int64_t>(bchi);
+                            const Fit f = fit_combo(m, c, bk, XT, a.shift);
+                            a.best.k[rr] = static_cast<int32_t>(bk);
+                            a.best.p0[rr] = f.v[0];
+                            a.best.p1[rr] = f.v[1];
+                            a.best.p2[rr] = f.v[2];
+                            a.best.chi2[rr] = static_cast<int64_t>(bchi);
                         }
                     } else {
                         const int slot = rb < 0 ? 0 : 1;
@@ -352,7 +463,13 @@ __global__ __launch_bounds__(WG) void k_fused(FArgs a) {
         // tile end: accepted counts per block of 4096 combinations (kept-list compaction)
         if (tid < (tile_len + kKeptBlock - 1) / kKeptBlock)
             a.kb_counts[tile_start / kKeptBlock + tid] = s_kb[tid];
+        if (tid == 0) {
+            s_tile = static_cast<int64_t>(gridDim.x) + ticket;
+            s_first = next_first;
+        }
         __syncthreads();
+        t = s_tile;
+        r_first = s_first;
     }
 }
 
@@ -410,7 +527,7 @@ FArgs make_args(const FusedLaunch &f) {
     a.shift = f.cfg.shift;
     a.n_sets = f.cfg.n_sets;
     a.cut = f.cfg.chi2_cut;
-    a.words = f.words;
+    a.coords = f.coords;
     a.roads = f.roads;
     a.d_n_roads = f.d_n_roads;
     a.d_n_combos = f.d_n_combos;
@@ -439,7 +556,8 @@ hipError_t launch_fused_t(const FArgs &a, int grid, hipStream_t s) {
 
 bool fused_tune_supported(const svt_tune &t) {
     const bool wg_ok = t.wg_size == 256 || t.wg_size == 512;
-    const bool ch_ok = t.chunk_roads == 16 || t.chunk_roads == 32 || t.chunk_roads == 64;
+    const bool ch_ok = (t.chunk_roads == 64 || t.chunk_roads == 128 || t.chunk_roads == 256) &&
+                       t.chunk_roads <= t.wg_size;
     const bool tile_ok = t.tile_combos >= kKeptBlock && t.tile_combos <= kKeptBlock * kMaxKb &&
                          t.tile_combos % kKeptBlock == 0;
     const bool occ_ok = t.wgs_per_cu >= 1 && t.wgs_per_cu <= 8;
@@ -450,12 +568,12 @@ hipError_t launch_fused(const FusedLaunch &f, hipStream_t s) {
     const FArgs a = make_args(f);
     const int grid = f.num_cus * f.tune.wgs_per_cu;
     const int wg = f.tune.wg_size, ch = f.tune.chunk_roads;
-    if (wg == 256 && ch == 16) return launch_fused_t<256, 16>(a, grid, s);
-    if (wg == 256 && ch == 32) return launch_fused_t<256, 32>(a, grid, s);
     if (wg == 256 && ch == 64) return launch_fused_t<256, 64>(a, grid, s);
-    if (wg == 512 && ch == 16) return launch_fused_t<512, 16>(a, grid, s);
-    if (wg == 512 && ch == 32) return launch_fused_t<512, 32>(a, grid, s);
+    if (wg == 256 && ch == 128) return launch_fused_t<256, 128>(a, grid, s);
+    if (wg == 256 && ch == 256) return launch_fused_t<256, 256>(a, grid, s);
     if (wg == 512 && ch == 64) return launch_fused_t<512, 64>(a, grid, s);
+    if (wg == 512 && ch == 128) return launch_fused_t<512, 128>(a, grid, s);
+    if (wg == 512 && ch == 256) return launch_fused_t<512, 256>(a, grid, s);
     return hipErrorInvalidValue;
 }
 

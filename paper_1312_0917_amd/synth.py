@@ -267,23 +267,43 @@ def _draw_block(rng, bank: Bank, n_ev: int, ev0: int, roads_spec, hits_spec, tru
                 true_road=true_road, t=t, slot=slot, rpe=rpe)
 
 
+_POOL_BANK = None
+
+
+def _set_pool_bank(bank):
+    global _POOL_BANK
+    _POOL_BANK = bank
+
+
+def _draw_job(job):
+    seed, blk, ev0, n, roads, hits, true_frac, layer_major = job
+    rng = np.random.default_rng([seed, blk])
+    return _draw_block(rng, _POOL_BANK, n, ev0, roads, hits, true_frac, layer_major)
+
+
 def make_sample(config: str | dict, seed: Optional[int] = None, n_events: Optional[int] = None,
                 bank: Optional[Bank] = None, true_frac: float = TRUE_ROAD_FRACTION,
-                layer_major: bool = False) -> Sample:
+                layer_major: bool = False, workers: int = 1) -> Sample:
     """Draw one of the benchmark configurations (``"c1"`` ... ``"c5"``) or a custom dict.
 
     Events are drawn in blocks of 256 with child streams ``default_rng([seed, block])``, so a
-    prefix of events does not depend on how many events follow it.
+    prefix of events does not depend on how many events follow it, nor on ``workers`` (blocks
+    drawn in that many processes).
     """
     cfg = dict(CONFIGS[config]) if isinstance(config, str) else dict(config)
     seed = cfg["seed"] if seed is None else seed
     n_ev = cfg["n_events"] if n_events is None else n_events
     bank = make_bank() if bank is None else bank
-    parts = []
-    for blk, ev0 in enumerate(range(0, n_ev, EVENTS_PER_BLOCK)):
-        rng = np.random.default_rng([seed, blk])
-        parts.append(_draw_block(rng, bank, min(EVENTS_PER_BLOCK, n_ev - ev0), ev0,
-                                 cfg["roads"], cfg["hits"], true_frac, layer_major))
+    jobs = [(seed, blk, ev0, min(EVENTS_PER_BLOCK, n_ev - ev0), cfg["roads"], cfg["hits"],
+             true_frac, layer_major) for blk, ev0 in enumerate(range(0, n_ev, EVENTS_PER_BLOCK))]
+    if workers > 1 and len(jobs) > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(workers, len(jobs)),
+                                         initializer=_set_pool_bank, initargs=(bank,)) as pool:
+            parts = pool.map(_draw_job, jobs, chunksize=1)
+    else:
+        _set_pool_bank(bank)
+        parts = [_draw_job(j) for j in jobs]
     cat = lambda k: (np.concatenate([p[k] for p in parts]) if parts else np.zeros(0))
     words = cat("words").astype(np.uint32)
     road_len = cat("road_len").astype(np.int64)

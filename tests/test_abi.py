@@ -65,7 +65,8 @@ def test_workspace_sizes_are_aligned_and_monotone():
     t = L.make_tune(8192, 64, 256, 4)
     assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, t) > 0
     assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, L.make_tune(1000, 64, 256, 4)) == -1
-    assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, L.make_tune(8192, 48, 256, 4)) == -1
+    assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, L.make_tune(65536, 64, 256, 4)) == -1
+    assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, L.make_tune(8192, 32, 256, 4)) == -1
 
 
 def test_host_argument_checks_reject_without_launching():
