@@ -125,9 +125,9 @@ typedef struct svt_best {
 
 /* Launch parameters of the persistent fused kernel; zeros pick the built-in defaults. */
 typedef struct svt_tune {
-    int32_t tile_combos;  /* combinations per work tile: a multiple of 4096, at most 16384 */
-    int32_t chunk_roads;  /* roads staged in LDS at once: 64, 128 or 256 (<= wg_size) */
-    int32_t wg_size;      /* 256 or 512 */
+    int32_t tile_combos;  /* combinations per work tile: 4096 or 8192 */
+    int32_t chunk_roads;  /* roads staged in LDS at once: 64 */
+    int32_t wg_size;      /* 256 or 512 (one loader wave, the rest fit) */
     int32_t wgs_per_cu;   /* persistent workgroups per compute unit, 1..8 */
 } svt_tune;
 

@@ -58,7 +58,6 @@ struct BatchWs {
     int64_t *rb;
     int64_t rbn;
     int32_t *tfr;
-    Partial *part;
     int64_t tiles_cap;
     int64_t *kb;
     int64_t kbn;
@@ -75,15 +74,14 @@ BatchWs carve_batch(Carver &c, int64_t word_cap, int64_t road_cap, int64_t combo
     w.rb = c.take<int64_t>(w.rbn);
     w.tiles_cap = ceil_div(combo_cap > 0 ? combo_cap : 1, tile) + 1;
     w.tfr = c.take<int32_t>(w.tiles_cap);
-    w.part = c.take<Partial>(2 * w.tiles_cap);
     w.kbn = ceil_div(combo_cap > 0 ? combo_cap : 1, kKeptBlock);
     w.kb = c.take<int64_t>(w.kbn);
-    w.coords = c.take<int16_t>(word_cap);
+    w.coords = c.take<int16_t>(word_cap + 16);  // slack for 16-byte reads of the last span
     return w;
 }
 
 svt_tune resolve_tune(const svt_tune *t) {
-    svt_tune r{4096, 128, 256, 4};
+    svt_tune r{4096, 64, 256, 3};
     if (t) {
         if (t->tile_combos) r.tile_combos = t->tile_combos;
         if (t->chunk_roads) r.chunk_roads = t->chunk_roads;
@@ -306,10 +304,12 @@ static svt_status batch_sequence(const FusedLaunch &f, const BatchWs &w, int64_t
                         combo_cap, 1, err, true, stream));
     SVT_TRY(launch_combo_begin(f.roads, nr, w.rbn, w.rb, f.tune.tile_combos, w.tfr, w.tiles_cap,
                                &f.best, err, stream));
+    if (d_n_kept) SVT_TRY(launch_zero(w.kb, w.kbn, stream));
     if (timing) SVT_TRY(hipEventRecord(g_ev_start, stream));
     SVT_TRY(launch_fused(f, stream));
     if (timing) SVT_TRY(hipEventRecord(g_ev_stop, stream));
-    SVT_TRY(launch_fixup(f, stream));
+    SVT_TRY(launch_best_finalize(f.roads, nr, f.rec, nc, f.best, f.cfg.chi2_cut, err, true,
+                                 stream));
     if (d_n_kept) {
         SVT_TRY(launch_scan(w.kb, 0, 1, nc, kKeptBlock, d_n_kept, nullptr, kept ? kept_cap : -1,
                             2, err, true, stream));
@@ -365,7 +365,6 @@ svt_status svt_process_batch(const svt_fconst *bank, const svt_config *cfg, cons
     f.accept = accept;
     f.best = *best;
     f.tile_first_road = w.tfr;
-    f.tile_part = w.part;
     f.kb_counts = w.kb;
     f.tile_counter = w.tile_counter;
     f.err = d_err;

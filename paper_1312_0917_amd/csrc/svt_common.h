@@ -25,13 +25,7 @@ __device__ inline uint64_t best_key(int64_t chi2, uint32_t k) {
     if (c > kKeyChiMax) c = kKeyChiMax;
     return (c << kKeyKBits) | k;
 }
-
-// Exact best-track summary of the part of a road seen by one tile.
-struct Partial {
-    uint64_t chi2;  // all ones: nothing accepted
-    uint32_t k;
-    uint32_t nacc;
-};
+constexpr int kMaxTile = 8192;            // combinations per tile of the fused kernel, at most
 
 // ---- error word: (class << 56) | index, smallest wins, all ones = none ------------------
 __device__ inline void report(uint64_t *err, uint32_t cls, uint64_t index) {
@@ -156,10 +150,11 @@ hipError_t launch_road_fill(const uint32_t *words, Sizes n_words, const int64_t 
                             hipStream_t s);
 hipError_t launch_combo_count(const svt_roads &roads, Sizes n_roads, int64_t grid_blocks,
                               int64_t *rb_sums, uint64_t *err, hipStream_t s);
+// best_init (nullable): every road's best key := none, n_accept := 0
 hipError_t launch_combo_begin(const svt_roads &roads, Sizes n_roads, int64_t grid_blocks,
                               const int64_t *rb_prefix, int64_t tile_combos,
                               int32_t *tile_first_road, int64_t tiles_cap,
-                              const svt_best *best_defaults, uint64_t *err, hipStream_t s);
+                              const svt_best *best_init, uint64_t *err, hipStream_t s);
 hipError_t launch_materialize(const svt_roads &roads, int64_t n_roads, const int64_t *d_n_combos,
                               int64_t combo_cap, int32_t *combo_road, uint32_t *combo_hits,
                               uint64_t *err, hipStream_t s);
@@ -190,7 +185,6 @@ struct FusedLaunch {
     uint8_t *accept;
     svt_best best;
     int32_t *tile_first_road;
-    Partial *tile_part;        // [tiles_cap][2]
     int64_t *kb_counts;        // per kKeptBlock combinations
     uint32_t *tile_counter;
     uint64_t *err;
@@ -200,7 +194,12 @@ struct FusedLaunch {
     int num_cus;
 };
 hipError_t launch_fused(const FusedLaunch &f, hipStream_t s);
-hipError_t launch_fixup(const FusedLaunch &f, hipStream_t s);
+hipError_t launch_zero(int64_t *p, int64_t n, hipStream_t s);
+// Per road: turn the best-track key left in best.chi2 into (k, chi2, p0..p2), reading the
+// parameters from the records (exact rescan of a road whose key saturated).
+hipError_t launch_best_finalize(const svt_roads &roads, Sizes n_roads, const svt_fitrec &rec,
+                                Sizes n_combos, const svt_best &best, int64_t cut,
+                                uint64_t *err, bool skip_if_error, hipStream_t s);
 hipError_t launch_batch_init(uint64_t *err, uint32_t *tile_counter, int64_t *d_n_kept,
                              hipStream_t s);
 bool fused_tune_supported(const svt_tune &t);

@@ -248,7 +248,7 @@ __global__ __launch_bounds__(kRoadBlock) void k_combo_begin(svt_roads roads, Siz
                                                             int64_t tile_combos,
                                                             int32_t *tile_first_road,
                                                             int64_t tiles_cap, svt_best best,
-                                                            int32_t write_defaults,
+                                                            int32_t init_best,
                                                             uint64_t *err) {
     __shared__ int64_t tmp[kRoadBlock / kWaveSize + 1];
     if (has_error(err)) return;
@@ -265,13 +265,9 @@ __global__ __launch_bounds__(kRoadBlock) void k_combo_begin(svt_roads roads, Siz
         for (int64_t t = (begin + tile_combos - 1) / tile_combos; t * tile_combos < begin + c; ++t)
             if (t < tiles_cap) tile_first_road[t] = static_cast<int32_t>(r);
     }
-    if (write_defaults && c == 0) {
+    if (init_best) {  // best-track key "none" (all ones) and no accepted combination yet
+        reinterpret_cast<uint64_t *>(best.chi2)[r] = UINT64_MAX;
         best.n_accept[r] = 0;
-        best.k[r] = -1;
-        best.p0[r] = INT32_MIN;
-        best.p1[r] = INT32_MIN;
-        best.p2[r] = INT32_MIN;
-        best.chi2[r] = INT64_MAX;
     }
 }
 
@@ -418,14 +414,19 @@ __global__ __launch_bounds__(kSegThreads) void k_select_mark(svt_config cfg, svt
     }
 }
 
-__global__ void k_best_finalize(svt_roads roads, int64_t n_roads, svt_fitrec rec,
-                                int64_t n_combos, svt_best best, int64_t cut) {
+__global__ void k_best_finalize(svt_roads roads, Sizes n_roads_s, svt_fitrec rec,
+                                Sizes n_combos_s, svt_best best, int64_t cut, uint64_t *err,
+                                int32_t skip_if_error) {
+    if (skip_if_error && has_error(err)) return;
+    const int64_t n_roads = load_size(n_roads_s);
+    const int64_t n_combos = load_size(n_combos_s);
     for (int64_t r = gtid(); r < n_roads; r += gstride()) {
         uint64_t key = reinterpret_cast<uint64_t *>(best.chi2)[r];
-        if (key != UINT64_MAX && (key >> kKeyKBits) == kKeyChiMax) {
+        const int64_t cb = roads.combo_begin[r];
+        const int64_t nc = roads.ncombo[r];
+        if (key != UINT64_MAX && (key >> kKeyKBits) == kKeyChiMax && cb >= 0 &&
+            nc <= (1 << kKeyKBits)) {
             // saturated key: exact scan of the road's records (chi2 >= 2^49 - 1 only)
-            const int64_t cb = roads.combo_begin[r];
-            const int64_t nc = roads.ncombo[r];
             uint64_t bchi = UINT64_MAX;
             int64_t bk = 0;
             for (int64_t k = 0; k < nc && cb + k < n_combos; ++k) {
@@ -454,7 +455,7 @@ __global__ void k_best_finalize(svt_roads roads, int64_t n_roads, svt_fitrec rec
             best.chi2[r] = INT64_MAX;
         } else {
             const int32_t k = static_cast<int32_t>(key & ((1u << kKeyKBits) - 1));
-            const int64_t g = roads.combo_begin[r] + k;
+            const int64_t g = cb + k;
             best.k[r] = k;
             best.chi2[r] = static_cast<int64_t>(key >> kKeyKBits);
             const bool in = g >= 0 && g < n_combos;
@@ -597,11 +598,19 @@ hipError_t launch_select(const svt_config &cfg, const svt_roads &roads, int64_t 
         hipLaunchKernelGGL(k_select_mark, dim3(g), dim3(kSegThreads), 0, s, cfg, roads, n_roads,
                            combo_road, rec.chi2, n_combos, accept, best, kb_counts, err);
     }
-    if (n_roads > 0) {
-        const int64_t g = clamp_grid((n_roads + 255) / 256, 1 << 16);
-        hipLaunchKernelGGL(k_best_finalize, dim3(g), dim3(256), 0, s, roads, n_roads, rec,
-                           n_combos, best, cfg.chi2_cut);
-    }
+    if (n_roads > 0)
+        return launch_best_finalize(roads, Sizes{n_roads, nullptr, n_roads}, rec,
+                                    Sizes{n_combos, nullptr, n_combos}, best, cfg.chi2_cut, err,
+                                    false, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_best_finalize(const svt_roads &roads, Sizes n_roads, const svt_fitrec &rec,
+                                Sizes n_combos, const svt_best &best, int64_t cut,
+                                uint64_t *err, bool skip_if_error, hipStream_t s) {
+    const int64_t g = clamp_grid((n_roads.cap + 255) / 256, 1 << 14);
+    hipLaunchKernelGGL(k_best_finalize, dim3(g), dim3(256), 0, s, roads, n_roads, rec, n_combos,
+                       best, cut, err, static_cast<int32_t>(skip_if_error));
     return hipGetLastError();
 }
 

@@ -62,10 +62,10 @@ def test_workspace_sizes_are_aligned_and_monotone():
         assert a > 0 and a % 256 == 0
         assert L.svt_unpack_workspace(n + 4096) >= a
     assert L.svt_unpack_workspace(-1) == -1
-    t = L.make_tune(8192, 64, 256, 4)
+    t = L.make_tune(8192, 64, 256, 3)
     assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, t) > 0
     assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, L.make_tune(1000, 64, 256, 4)) == -1
-    assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, L.make_tune(65536, 64, 256, 4)) == -1
+    assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, L.make_tune(16384, 64, 256, 4)) == -1
     assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, L.make_tune(8192, 32, 256, 4)) == -1
 
 

@@ -17,8 +17,8 @@ from paper_1312_0917_amd import synth
 pytestmark = pytest.mark.gpu
 
 CFG = oracle.make_config(chi2_cut=synth.DEFAULT_CHI2_CUT)
-TUNES = [L.make_tune(4096, 64, 256, 2), L.make_tune(8192, 128, 256, 4),
-         L.make_tune(16384, 256, 512, 2), L.make_tune(12288, 64, 512, 1)]
+TUNES = [L.make_tune(4096, 64, 256, 2), L.make_tune(8192, 64, 256, 3),
+         L.make_tune(4096, 64, 512, 1), L.make_tune(8192, 64, 512, 2)]
 
 
 @pytest.fixture(scope="module")
