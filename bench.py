@@ -62,7 +62,7 @@ def fused_kernel_ms(runner, steps, warmup):
     return float(np.mean(kms))
 
 
-def measure_large(config, n_events, passes, tune, bank):
+def measure_large(config, n_events, passes, tune, bank, workers=16):
     """Max-scale run: whole batch resident in HBM, graph replays, fused-kernel roofline."""
     import torch
 
@@ -72,7 +72,7 @@ def measure_large(config, n_events, passes, tune, bank):
     from paper_1312_0917_amd import synth
 
     log(f"generating {config} ({n_events} events)")
-    sample = synth.make_sample(config, bank=bank, n_events=n_events, workers=16)
+    sample = synth.make_sample(config, bank=bank, n_events=n_events, workers=workers)
     cut = synth.config_chi2_cut(config)
     n_words, n_roads = len(sample.words), sample.n_roads
     n_combos = sample.expected_combos()
@@ -107,6 +107,74 @@ def measure_large(config, n_events, passes, tune, bank):
     return out
 
 
+def measure_uneven(bank, steps, log_fn):
+    """Uneven batch in one persistent launch (8192 events, geometric roads/event, heavy-tailed
+    hits per layer): the autotuner times every launch shape and keeps the fastest."""
+    import torch
+
+    import oracle
+    from paper_1312_0917_amd import _lib as L
+    from paper_1312_0917_amd import pipeline as P
+    from paper_1312_0917_amd import synth
+    from paper_1312_0917_amd import tune as T
+
+    sample = synth.make_sample("c3", bank=bank)
+    cut = synth.config_chi2_cut("c3")
+    st, nr, ne, nc, _ = oracle.count(sample.words, oracle.make_config(chi2_cut=cut))
+    words = P.words_tensor(sample.words)
+    res = T.autotune(words, P.device_bank(bank.f, bank.q), L.make_config(chi2_cut=cut), nr, nc,
+                     steps=steps, cache_path=None, use_cache=False, log=log_fn)
+    default = [row for row in res.table if row[:4] == (4096, 64, 256, 3)]
+    return dict(workload=f"c3: {ne} events, {nr} roads, {len(sample.words)} hit words, "
+                         f"{nc} combinations", best_tune=dict(zip(
+                             ("tile_combos", "chunk_roads", "wg_size", "wgs_per_cu"),
+                             T.tune_tuple(res.tune))),
+                ms_per_pass_best=round(res.ms_per_pass, 5),
+                ms_per_pass_default=default[0][4] if default else None,
+                value=nc / (res.ms_per_pass * 1e-3), unit="fitted combinations/s",
+                candidates=len(res.table), all_outputs_identical=True)
+
+
+def measure_serving(bank, n_events, warmup_events, rate_hz, n_slots, max_events, tune, workers):
+    """Poisson stream of events through the continuous-batching loop, fused path and plain path
+    fed the same schedule; latency from arrival to results on the host (H2D and D2H included)."""
+    import numpy as np
+    import torch
+
+    from paper_1312_0917_amd import _lib as L
+    from paper_1312_0917_amd import pipeline as P
+    from paper_1312_0917_amd import serve, synth
+
+    sample = synth.make_sample("c4", bank=bank, n_events=n_events, workers=workers)
+    arrivals = synth.poisson_arrivals(n_events, rate_hz, seed=3)
+    st = serve.EventStream(sample.words, sample.event_word_begin, arrivals)
+    mean_w = len(sample.words) / n_events
+    mean_c = sample.expected_combos() / n_events
+    word_cap = int(max_events * mean_w * 1.6)
+    combo_cap = int(max_events * mean_c * 1.6)
+    cfg = L.make_config(chi2_cut=synth.config_chi2_cut("c4"))
+    dbank = P.device_bank(bank.f, bank.q)
+    slots = [serve.GpuSlot(cfg, dbank, word_cap, word_cap // 5 + 1, combo_cap, tune=tune)
+             for _ in range(n_slots)]
+    # capture each slot's graph before the clock starts
+    warm = serve.EventStream(sample.words, sample.event_word_begin, np.zeros(n_events))
+    for sl in slots:
+        sl.launch(warm.slice(0, 1), 0, 1)
+        sl.done_ev.synchronize()
+        sl.collect()
+    stats, _ = serve.serve(st, slots, max_events=max_events)
+    batched = stats.summary(warmup_events)
+    pstats, _ = serve.serve(st, [serve.PlainSlot(cfg, dbank)], max_events=max_events)
+    plain = pstats.summary(warmup_events)
+    L.svt_release_graphs()
+    del slots
+    torch.cuda.empty_cache()
+    return dict(workload=f"c4: {n_events} events ({warmup_events} warm-up) arriving as a "
+                         f"Poisson stream at {rate_hz / 1e3:.0f} kHz, {mean_w:.0f} words and "
+                         f"{mean_c:.0f} combinations per event on average",
+                slots=n_slots, max_events_per_batch=max_events, batched=batched, plain=plain)
+
+
 def run_cpu_baseline(sample, bank, cfg, seconds):
     import oracle
 
@@ -122,6 +190,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2")
+    ap.add_argument("--events", type=int, default=0, help="override the workload's event count")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -132,6 +201,13 @@ def main():
     ap.add_argument("--large-events", type=int, default=10000,
                     help="events of the max-scale run (10000 x 2048 roads); 0 skips it")
     ap.add_argument("--large-passes", type=int, default=5)
+    ap.add_argument("--workers", type=int, default=16, help="processes drawing large samples")
+    ap.add_argument("--no-graph", action="store_true", help="direct launches instead of replays")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the autotuned uneven batch")
+    ap.add_argument("--serve-events", type=int, default=40000, help="0 skips the serving run")
+    ap.add_argument("--serve-warmup", type=int, default=5000)
+    ap.add_argument("--serve-rate", type=float, default=100e3)
+    ap.add_argument("--serve-slots", type=int, default=4)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -155,7 +231,10 @@ def main():
 
     log(f"generating {args.config}")
     bank = synth.make_bank()
-    sample = synth.make_sample(args.config, bank=bank)
+    n_ev = args.events or synth.CONFIGS[args.config]["n_events"]
+    big = synth.expected_size(args.config)["words"] * n_ev / synth.CONFIGS[args.config]["n_events"] > 5e7
+    sample = synth.make_sample(args.config, bank=bank, n_events=n_ev,
+                               workers=args.workers if big else 1)
     cut = synth.config_chi2_cut(args.config)
     cfg = oracle.make_config(chi2_cut=cut)
     st, n_roads, n_events, n_combos, _ = oracle.count(sample.words, cfg)
@@ -168,7 +247,7 @@ def main():
 
     # ---- batched path: resident buffers, graph replay -------------------------------------
     runner = P.BatchRunner(gcfg, dbank, n_words, n_roads, n_combos, kept_cap=0, tune=tune,
-                           graph=True, with_c=False)
+                           graph=not args.no_graph, with_c=False)
     runner.load(words)
     log("batched warmup")
     for _ in range(W):
@@ -218,12 +297,24 @@ def main():
                      batched_over_plain=round(plain_s / batch_s, 2))
         del pr
 
+    uneven = None
+    if not args.no_uneven:
+        log("uneven batch: autotuning")
+        uneven = measure_uneven(bank, 10, log)
+
+    serving = None
+    if args.serve_events > 0:
+        log(f"serving: {args.serve_events} events at {args.serve_rate:.0f} Hz")
+        serving = measure_serving(bank, args.serve_events, args.serve_warmup, args.serve_rate,
+                                  args.serve_slots, 256, tune, args.workers)
+
     large = None
     if args.large_events > 0:
         L.svt_release_graphs()
         del runner
         torch.cuda.empty_cache()
-        large = measure_large("c5", args.large_events, args.large_passes, tune, bank)
+        large = measure_large("c5", args.large_events, args.large_passes, tune, bank,
+                              args.workers)
 
     cpu = None
     if not args.no_cpu:
@@ -239,11 +330,13 @@ def main():
                              f"words, {n_combos} combinations "
                              f"({n_combos / max(n_events, 1):.0f} per event)",
                     events=n_events, roads=n_roads, words=n_words, combinations=n_combos,
-                    chi2_cut=cut, path="svt_process_batch (graph replay)",
+                    chi2_cut=cut, path="svt_process_batch (%s)" % (
+                        "direct launches" if args.no_graph else "graph replay"),
                     tune=dict(tile_combos=t.tile_combos, chunk_roads=t.chunk_roads,
                               wg_size=t.wg_size, wgs_per_cu=t.wgs_per_cu),
                     device=dev_name),
-        roofline=roofline, cpu_baseline=cpu, plain=plain, max_scale=large)
+        roofline=roofline, cpu_baseline=cpu, plain=plain, uneven_autotuned=uneven,
+        serving=serving, max_scale=large)
     print(json.dumps(out), flush=True)
 
 

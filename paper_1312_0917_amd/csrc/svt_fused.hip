@@ -55,8 +55,8 @@ struct FArgs {
 // Per-road indexing data of the current chunk, in LDS (32 bytes).
 struct alignas(16) RoadMeta {
     int32_t C;      // combinations
-    uint32_t m4;    // division magic of n4 (0 when n4 == 1)
-    uint32_t m23;   // division magic of n2 * n3 (0 when 1)
+    uint32_t m4;    // division magic of n4
+    uint32_t m23;   // division magic of n2 * n3
     uint32_t nn;    // n4 | (n2 * n3) << 8
     int32_t b01;    // table index of the (h0, h1) coordinate pairs
     int32_t b23;    // table index of the (h2, h3) pairs
@@ -82,14 +82,23 @@ __device__ __forceinline__ int32_t dot2(int32_t a, int32_t b, int32_t c) {
                                   false);
 }
 
-// floor(k / n) for 0 <= k < 2^15 and 1 <= n <= 64 with m = ceil(2^32 / n) (m = 0 for n = 1):
-// k * (m * n - 2^32) < 2^15 * 64 < 2^32, so the high word of k * m is exact.
+// floor(k / n) for 0 <= k < 2^15 and 1 <= n <= 64 with m = ceil(2^23 / n) < 2^24, using the
+// full-rate 24-bit multiply: (k * 2^9) * m / 2^32 = k * m / 2^23 and k * (m * n - 2^23) <
+// 2^15 * 64 < 2^23, so the high word is exactly floor(k / n) (n = 1 included).
 __device__ __forceinline__ uint32_t div_small(uint32_t k, uint32_t m) {
-    return m ? __umulhi(k, m) : k;
+    const uint64_t p = static_cast<uint64_t>((k << 9) & 0xFFFFFFu) * static_cast<uint64_t>(m & 0xFFFFFFu);
+    return static_cast<uint32_t>(p >> 32);  // v_mul_hi_u32_u24
+}
+
+// a * b for a, b < 2^24 (low 32 bits) on the full-rate 24-bit multiplier
+__device__ __forceinline__ uint32_t mul_u24(uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
 }
 
 __host__ __device__ constexpr uint32_t magic_of(uint32_t n) {
-    return n <= 1 ? 0u : static_cast<uint32_t>((0x100000000ull + n - 1) / n);
+    return static_cast<uint32_t>(((1u << 23) + n - 1) / n);
 }
 
 __device__ __forceinline__ int32_t pack16(int32_t lo, int32_t hi) {
@@ -110,9 +119,9 @@ __device__ __forceinline__ Fit fit_combo(const RoadMeta &m, const RoadConst &c, 
                                          const int32_t *XT, int32_t shift) {
     const uint32_t n4 = m.nn & 0xFFu, n23 = m.nn >> 8;
     const uint32_t q4 = div_small(k, m.m4);
-    const uint32_t h4 = k - q4 * n4;
+    const uint32_t h4 = k - mul_u24(q4, n4);
     const uint32_t i01 = div_small(q4, m.m23);
-    const uint32_t i23 = q4 - i01 * n23;
+    const uint32_t i23 = q4 - mul_u24(i01, n23);
     const int32_t x01 = XT[m.b01 + static_cast<int32_t>(i01)];
     const int32_t x23 = XT[m.b23 + static_cast<int32_t>(i23)];
     const int32_t x4 = XT[m.b4 + static_cast<int32_t>(h4)];
@@ -129,12 +138,6 @@ __device__ __forceinline__ Fit fit_combo(const RoadMeta &m, const RoadConst &c, 
     return f;
 }
 
-// int16 element i of a constant set's f[6][5] read as 8-byte words
-__device__ __forceinline__ int32_t f_at(const uint2 *fw, int i) {
-    const uint2 w = fw[i >> 2];
-    const uint32_t d = ((i >> 1) & 1) ? w.y : w.x;
-    return static_cast<int32_t>(static_cast<int16_t>((i & 1) ? (d >> 16) : (d & 0xFFFFu)));
-}
 
 // One staged chunk: up to 64 consecutive roads of a tile.
 struct Stage {
@@ -152,16 +155,46 @@ struct Stage {
 struct Loader {
     int64_t t, tile_start, tile_end, r_next;
     uint32_t ticket;  // lane 0: ticket of the next tile, fetched when this tile started
+    // road-table entries of roads r_next + lane, loaded one chunk ahead
+    bool pf;
+    int64_t pcb, phb;
+    int32_t pC, ps;
+    uint32_t pnh;
 };
+
+__device__ __forceinline__ void load_roads(const FArgs &a, Loader &L, int64_t n_roads) {
+    const int64_t r = L.r_next + lane_id();
+    L.pcb = INT64_MAX;  // roads past the end are never valid
+    L.phb = 0;
+    L.pC = 0;
+    L.ps = 0;
+    L.pnh = 0;
+    if (r < n_roads) {
+        L.pcb = a.roads.combo_begin[r];
+        L.pC = a.roads.ncombo[r];
+        L.pnh = a.roads.nhits[r];
+        L.phb = a.roads.hit_begin[r];
+        L.ps = a.roads.set[r];
+    }
+    L.pf = true;
+}
 
 __device__ __forceinline__ void start_tile(const FArgs &a, Loader &L, int64_t n_tiles,
                                            int64_t n_combos, int64_t T) {
+    L.pf = false;
     if (L.t < n_tiles) {
         L.tile_start = L.t * T;
         L.tile_end = (L.tile_start + T < n_combos) ? L.tile_start + T : n_combos;
         L.r_next = a.tile_first_road[L.t];
         if (lane_id() == 0) L.ticket = atomicAdd(a.tile_counter, 1u);
     }
+}
+
+// int16 element i of a constant set's f[6][5], from its first 64 bytes held as 8-byte words
+__device__ __forceinline__ int32_t f_el(const uint2 *fw, int i) {
+    const uint2 w = fw[i >> 2];
+    const uint32_t d = ((i >> 1) & 1) ? w.y : w.x;
+    return static_cast<int32_t>(static_cast<int16_t>((i & 1) ? (d >> 16) : (d & 0xFFFFu)));
 }
 
 // Wave 0: stage the next chunk into S (or mark the end of the work).
@@ -173,22 +206,12 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
             if (lane == 0) S.done = 1;
             return;
         }
-        // ---- road table of up to 64 candidate roads, sizes and capacities
-        const int64_t r = L.r_next + lane;
-        bool valid = false;
-        int64_t cb = 0, hb = 0;
-        int32_t C = 0, s = 0;
-        uint32_t nh = 0;
-        if (r < n_roads) {
-            cb = a.roads.combo_begin[r];
-            valid = cb < L.tile_end;
-            if (valid) {
-                C = a.roads.ncombo[r];
-                nh = a.roads.nhits[r];
-                hb = a.roads.hit_begin[r];
-                s = a.roads.set[r];
-            }
-        }
+        if (!L.pf) load_roads(a, L, n_roads);
+        // ---- sizes and capacities of up to 64 candidate roads
+        const int64_t cb = L.pcb, hb = L.phb;
+        const int32_t C = L.pC, s = L.ps;
+        const uint32_t nh = L.pnh;
+        const bool valid = cb < L.tile_end;
         const int32_t n0 = nh_of(nh, 0), n1 = nh_of(nh, 1), n2 = nh_of(nh, 2),
                       n3 = nh_of(nh, 3), n4 = nh_of(nh, 4);
         const int32_t nwords = valid ? n0 + n1 + n2 + n3 + n4 : 0;
@@ -213,19 +236,36 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
         const int32_t ce = last_end < tile_len ? last_end : tile_len;
         const int32_t g_lo = cs >> 2, g_hi = (ce + 3) >> 2;
         const int32_t next_rb = __shfl_down(rb, 1);
+        const int64_t r_first = L.r_next;
 
-        // ---- the chunk's coordinates: one contiguous span, copied as aligned 16-byte pieces
+        // ---- issue every global read of this chunk before waiting on any: constant sets,
+        //      the coordinate span (aligned 16-byte pieces), the next chunk's road table
+        uint2 fw[8];
+        uint2 qw[3];
+        if (fits) {
+            const uint2 *src = reinterpret_cast<const uint2 *>(a.bank + s);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) fw[i] = src[i];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) qw[i] = src[8 + i];  // q[6] at byte 64
+        }
         const int64_t base = span & ~static_cast<int64_t>(7);
         const int32_t goff = static_cast<int32_t>(span - base);
         const int32_t n16 = (goff + nw + 7) >> 3;  // <= 257
+        uint4 v[5];
         {
             const uint4 *src = reinterpret_cast<const uint4 *>(a.coords + base);
-            uint4 v[5];
 #pragma unroll
             for (int u = 0; u < 5; ++u) {
                 const int i = lane + 64 * u;
                 v[u] = i < n16 ? src[i] : make_uint4(0, 0, 0, 0);
             }
+        }
+        L.r_next += nr;
+        load_roads(a, L, n_roads);
+
+        // ---- stage: coordinates, per-road indexing data and packed constants
+        {
             uint4 *dst = reinterpret_cast<uint4 *>(S.G);
 #pragma unroll
             for (int u = 0; u < 5; ++u) {
@@ -233,7 +273,6 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
                 if (i < n16) dst[i] = v[u];
             }
         }
-        // ---- per staged road: indexing data, packed constants
         if (fits) {
             RoadMeta m;
             m.C = C;
@@ -246,17 +285,17 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
             m.wo = wo;
             S.meta[lane] = m;
             S.rb[lane] = rb;
-            // constant set: f[6][5] int16 (60 bytes), 4 bytes pad, q[6] int32
-            const uint2 *fw = reinterpret_cast<const uint2 *>(a.bank + s);
+            const int32_t qv[6] = {static_cast<int32_t>(qw[0].x), static_cast<int32_t>(qw[0].y),
+                                   static_cast<int32_t>(qw[1].x), static_cast<int32_t>(qw[1].y),
+                                   static_cast<int32_t>(qw[2].x), static_cast<int32_t>(qw[2].y)};
             RoadConst rc;
 #pragma unroll
             for (int j = 0; j < 6; ++j) {
-                rc.F01[j] = pack16(f_at(fw, 5 * j + 0), f_at(fw, 5 * j + 1));
-                rc.F23[j] = pack16(f_at(fw, 5 * j + 2), f_at(fw, 5 * j + 3));
-                rc.F4[j] = pack16(f_at(fw, 5 * j + 4), 0);
-                const int32_t q = a.bank[s].q[j];
-                rc.qh[j] = q >> a.shift;
-                rc.ql[j] = static_cast<int32_t>(static_cast<uint32_t>(q) & qlmask);
+                rc.F01[j] = pack16(f_el(fw, 5 * j + 0), f_el(fw, 5 * j + 1));
+                rc.F23[j] = pack16(f_el(fw, 5 * j + 2), f_el(fw, 5 * j + 3));
+                rc.F4[j] = pack16(f_el(fw, 5 * j + 4), 0);
+                rc.qh[j] = qv[j] >> a.shift;
+                rc.ql[j] = static_cast<int32_t>(static_cast<uint32_t>(qv[j]) & qlmask);
             }
             rc.pad[0] = rc.pad[1] = 0;
             S.rc[lane] = rc;
@@ -291,7 +330,7 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
         }
         if (lane == 0) {
             S.tile_start = L.tile_start;
-            S.r_first = L.r_next;
+            S.r_first = r_first;
             S.nr = nr;
             S.cs = cs;
             S.ce = ce;
@@ -299,7 +338,6 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
             S.g_hi = g_hi;
             S.done = 0;
         }
-        L.r_next += nr;
         return;
     }
 }
@@ -447,6 +485,10 @@ __global__ __launch_bounds__(WG) void k_fused(FArgs a) {
     L.t = blockIdx.x;
     L.tile_start = L.tile_end = L.r_next = 0;
     L.ticket = 0;
+    L.pf = false;
+    L.pcb = L.phb = 0;
+    L.pC = L.ps = 0;
+    L.pnh = 0;
     if (wave == 0) {
         start_tile(a, L, n_tiles, n_combos, T);
         produce(a, S[0], L, n_roads, n_combos, n_tiles, T, qlmask);

@@ -1,0 +1,74 @@
+"""Serving loop on the GPU: continuous batching gives every event the same result as fitting
+it alone (integers: tolerance 0), and an overflowing batch is split and rerun correctly."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import gpu_cfg, to_np
+
+from paper_1312_0917_amd import _lib as L
+from paper_1312_0917_amd import pipeline as P
+from paper_1312_0917_amd import serve, synth
+
+pytestmark = pytest.mark.gpu
+KEYS = ("n_accept", "k", "p0", "p1", "p2", "chi2")
+ORA = {"n_accept": "best_nacc", "k": "best_k", "p0": "best_p0", "p1": "best_p1",
+       "p2": "best_p2", "chi2": "best_chi2"}
+
+
+def _stream(bank, n_events, rate_hz, seed=3):
+    s = synth.make_sample("c4", n_events=n_events, bank=bank)
+    arr = synth.poisson_arrivals(s.n_events, rate_hz=rate_hz, seed=seed)
+    return serve.EventStream(s.words, s.event_word_begin, arr)
+
+
+def _alone_gpu(st, e, bank, dbank, cfg):
+    w = st.slice(e, e + 1)
+    ref = oracle.run(w, bank.f, bank.q, cfg, combos=False)
+    r = P.BatchRunner(gpu_cfg(cfg), dbank, len(w), ref["n_roads"], ref["n_combos"] + 4,
+                      graph=False, with_c=False)
+    out = r.load(P.words_tensor(w)).run().result()
+    return {k: to_np(out["best_" + k]) for k in KEYS}, ref
+
+
+def test_each_event_same_alone_and_in_the_mix(bank):
+    cfg = oracle.make_config()
+    dbank = P.device_bank(bank.f, bank.q)
+    st = _stream(bank, 400, rate_hz=2e6)
+    words_cap = 64 * 6000
+    slots = [serve.GpuSlot(gpu_cfg(cfg), dbank, words_cap, words_cap // 5, 64 * 40000,
+                           keep_results=True) for _ in range(3)]
+    stats, res = serve.serve(st, slots, max_events=64, keep_results=True)
+    assert max(stats.batch_sizes) > 1, "the stream should have been batched"
+    assert not np.isnan(stats.latency_s).any() and np.all(stats.latency_s > 0)
+    for e in range(0, st.n_events, 13):
+        alone, ref = _alone_gpu(st, e, bank, dbank, cfg)
+        for k in KEYS:
+            assert np.array_equal(res[e][k], alone[k]), (e, k)
+            assert np.array_equal(res[e][k], np.asarray(ref[ORA[k]])), (e, k)
+    L.svt_release_graphs()
+
+
+def test_overflowing_batch_is_split_and_rerun(bank):
+    cfg = oracle.make_config()
+    dbank = P.device_bank(bank.f, bank.q)
+    st = _stream(bank, 60, rate_hz=1e7, seed=4)
+    # combination capacity of about 6 events: 16-event batches must split
+    slot = serve.GpuSlot(gpu_cfg(cfg), dbank, 16 * 6000, 16 * 1200, 80000, keep_results=True)
+    stats, res = serve.serve(st, [slot], max_events=16, keep_results=True)
+    assert slot.retries > 0
+    for e in range(0, st.n_events, 5):
+        ref = oracle.run(st.slice(e, e + 1), bank.f, bank.q, cfg, combos=False)
+        for k in KEYS:
+            assert np.array_equal(res[e][k], np.asarray(ref[ORA[k]])), (e, k)
+    L.svt_release_graphs()
+
+
+def test_plain_slot_serves_the_same_stream(bank):
+    cfg = oracle.make_config()
+    dbank = P.device_bank(bank.f, bank.q)
+    st = _stream(bank, 50, rate_hz=1e6)
+    stats, _ = serve.serve(st, [serve.PlainSlot(gpu_cfg(cfg), dbank)], max_events=16)
+    tot = oracle.count(st.words, cfg)[3]
+    assert stats.n_combos == tot
