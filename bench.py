@@ -160,7 +160,7 @@ def measure_serving(bank, n_events, warmup_events, rate_hz, n_slots, max_events,
     warm = serve.EventStream(sample.words, sample.event_word_begin, np.zeros(n_events))
     for sl in slots:
         sl.launch(warm.slice(0, 1), 0, 1)
-        sl.done_ev.synchronize()
+        sl._wait()
         sl.collect()
     stats, _ = serve.serve(st, slots, max_events=max_events)
     batched = stats.summary(warmup_events)

@@ -139,7 +139,12 @@ def split_by_event(road_event: np.ndarray, arrays: dict, n_events: int) -> list:
 
 
 class GpuSlot:
-    """Fused persistent pass on its own stream: pinned words -> H2D -> graph replay -> D2H."""
+    """Fused persistent pass on its own stream: pinned words -> H2D -> graph replay -> D2H.
+
+    Results come back in two steps so that only what the batch produced crosses PCIe: the
+    sizes and error word first, then (once they are on the host) exactly n_roads entries of
+    the per-road best tracks, their event ordinals and constant sets.
+    """
 
     BEST_KEYS = ("n_accept", "k", "p0", "p1", "p2", "chi2")
 
@@ -163,12 +168,14 @@ class GpuSlot:
                        for k, v in self.runner.best.items()}
         self.h_event = torch.empty(road_cap, dtype=torch.int32, pin_memory=True)
         self.h_set = torch.empty(road_cap, dtype=torch.int32, pin_memory=True)
+        self.sizes_ev = torch.cuda.Event()
         self.done_ev = torch.cuda.Event()
         self.retries = 0
         self.batch = None
+        self.stage = 0  # 1: sizes in flight, 2: results in flight, 3: complete
 
     def fits(self, n_words: int, n_events: int) -> bool:
-        # roads need at least one word each; combinations are checked on the device and a
+        # every road holds at least one word; combinations are checked on the device and a
         # batch that overflows is split and run again
         return n_words <= self.word_cap
 
@@ -184,46 +191,53 @@ class GpuSlot:
         with torch.cuda.stream(self.stream):
             self.h_sizes.copy_(r.d_n, non_blocking=True)
             self.h_err.copy_(r.d_err, non_blocking=True)
-            for k in self.BEST_KEYS:
-                self.h_best[k].copy_(r.best[k], non_blocking=True)
-            self.h_event.copy_(r.roads["event"], non_blocking=True)
-            self.h_set.copy_(r.roads["set"], non_blocking=True)
-        self.done_ev.record(self.stream)
+        self.sizes_ev.record(self.stream)
+        self.stage = 1
+
+    def _error(self):
+        from . import _lib as L
+
+        err = int(self.h_err[0]) & L.SVT_NO_ERROR
+        return L.error_decode(err) if err != L.SVT_NO_ERROR else (0, -1)
+
+    def poll(self) -> bool:
+        if self.stage == 1:
+            if not self.sizes_ev.query():
+                return False
+            nr = int(self.h_sizes[1])
+            if self._error()[0] != 0 or not 0 <= nr <= self.road_cap:
+                self.stage = 3
+                return True
+            torch, r = self.torch, self.runner
+            with torch.cuda.stream(self.stream):
+                for k in self.BEST_KEYS:
+                    self.h_best[k][:nr].copy_(r.best[k][:nr], non_blocking=True)
+                self.h_event[:nr].copy_(r.roads["event"][:nr], non_blocking=True)
+                self.h_set[:nr].copy_(r.roads["set"][:nr], non_blocking=True)
+            self.done_ev.record(self.stream)
+            self.stage = 2
+            return False
+        if self.stage == 2:
+            if not self.done_ev.query():
+                return False
+            self.stage = 3
+        return self.stage == 3
+
+    def _wait(self):
+        self.sizes_ev.synchronize()
+        while not self.poll():
+            self.done_ev.synchronize()
 
     def launch(self, words: np.ndarray, e0: int, e1: int):
         self.batch = (words, e0, e1)
         self._enqueue(words)
 
-    def poll(self) -> bool:
-        return self.done_ev.query()
-
-    def _run_sync(self, words: np.ndarray):
-        self._enqueue(words)
-        self.done_ev.synchronize()
-        return self._gather(len(words), None)
-
-    def _gather(self, n_words, n_events):
-        from . import _lib as L
-
-        err = int(self.h_err[0]) & L.SVT_NO_ERROR
-        sizes = self.h_sizes.tolist()
-        if err != L.SVT_NO_ERROR:
-            st, idx = L.error_decode(err)
-            return st, idx, sizes, None
-        nr = sizes[1]
-        per_event = None
-        if self.keep:
-            arrays = {k: self.h_best[k][:nr].numpy().copy() for k in self.BEST_KEYS}
-            arrays["set"] = self.h_set[:nr].numpy().copy()
-            ev = self.h_event[:nr].numpy()
-            per_event = split_by_event(ev, arrays, int(ev[-1]) + 1 if nr else 0)
-        return 0, -1, sizes, per_event
-
     def collect(self):
         from . import _lib as L
 
         words, e0, e1 = self.batch
-        st, idx, sizes, per_event = self._gather(len(words), e1 - e0)
+        st, idx = self._error()
+        sizes = self.h_sizes.tolist()
         if st == L.SVT_ERR_CAPACITY and e1 - e0 > 1:
             # more roads or combinations than this slot holds: split at an event boundary
             # and run the halves synchronously (rare when slots are sized for the stream)
@@ -231,12 +245,16 @@ class GpuSlot:
             return self._split_run(words, e0, e1)
         if st != 0:
             raise RuntimeError(f"batch {e0}-{e1}: {L.status_name(st)} at {idx}")
-        if self.keep and per_event is not None and len(per_event) < e1 - e0:
-            per_event += [None] * (e1 - e0 - len(per_event))
+        per_event = None
+        if self.keep:
+            nr = sizes[1]
+            arrays = {k: self.h_best[k][:nr].numpy().copy() for k in self.BEST_KEYS}
+            arrays["set"] = self.h_set[:nr].numpy().copy()
+            per_event = split_by_event(self.h_event[:nr].numpy(), arrays, e1 - e0)
         return sizes[2], per_event
 
     def _split_run(self, words, e0, e1):
-        # the words of events e0..e1 are contiguous; find the event boundaries from the tags
+        # the words of events e0..e1 are contiguous; event boundaries are event-tag changes
         et = (words >> 24).astype(np.int64)
         starts = np.concatenate([[0], np.nonzero(et[1:] != et[:-1])[0] + 1, [len(words)]])
         mid = (e1 - e0) // 2
@@ -245,7 +263,7 @@ class GpuSlot:
             part = words[starts[a]:starts[b]]
             self.batch = (part, e0 + a, e0 + b)
             self._enqueue(part)
-            self.done_ev.synchronize()
+            self._wait()
             nc, pe = self.collect()
             total += nc
             res += pe if pe is not None else []
