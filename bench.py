@@ -12,7 +12,9 @@ kernel (HIP events on its own stream), and the CPU oracle timed on the host as a
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -22,6 +24,52 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "fitted combinations/s and p50/p99 event latency (µs), batched vs plain"
+
+
+PROFILES = os.path.join(ROOT, "profiles")
+# sources the fused kernel is compiled from: recorded HBM counters are valid while these match
+FUSED_SOURCES = [os.path.join(ROOT, "paper_1312_0917_amd", "csrc", f)
+                 for f in ("svt_fused.hip", "svt_common.h")]
+
+
+def fused_source_digest():
+    h = hashlib.sha1()
+    for f in FUSED_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(config, n_events):
+    """HBM bytes per launch of the fused kernel from the committed counter summary for this
+    workload (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each scaled by what the counter
+    reads for a plain copy of known size).  None when there is no summary for the workload or
+    the kernel's sources changed since the counters were taken."""
+    path = os.path.join(PROFILES, f"k_fused_{config}_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    kv = dict(re.findall(r"^([a-z_0-9]+): (\S+)\s*$", open(path).read(), flags=re.M))
+    try:
+        if kv["kernel_source_sha1"] != fused_source_digest() or int(kv["events"]) != n_events:
+            return None
+        fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
+        write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])
+    except (KeyError, ValueError):
+        return None
+    return int(round((fetch + write) * 1024))
+
+
+def copy_calibration(n_bytes=1 << 30, reps=3):
+    """Plain device copy of a known size, run under the HBM byte counters to scale them."""
+    import torch
+
+    torch.cuda.set_device(0)
+    x = torch.ones(n_bytes, dtype=torch.uint8, device="cuda")
+    y = torch.empty(n_bytes, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_bytes=n_bytes, copies=reps)), flush=True)
 
 
 def log(msg):
@@ -99,7 +147,8 @@ def measure_large(config, n_events, passes, tune, bank, workers=16):
                value=n_combos / dt, unit="fitted combinations/s", ms_per_pass=round(dt * 1e3, 4),
                passes=passes,
                roofline=dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                             frac=round(ach / HBM_PEAK_GBS, 4), kernel="k_fused",
+                             frac=round(ach / HBM_PEAK_GBS, 4),
+                             traffic=recorded_traffic(config, n_events), kernel="k_fused",
                              kernel_ms=round(k_ms, 4), algorithmic_bytes=alg,
                              bytes_per_combination=round(alg / n_combos, 3)))
     del runner
@@ -208,6 +257,8 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=5000)
     ap.add_argument("--serve-rate", type=float, default=100e3)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB three times (scale for the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -215,6 +266,10 @@ def main():
               f"(the fitter shards by event range with no exchange; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import numpy as np
     import torch
@@ -243,7 +298,7 @@ def main():
     gcfg = L.make_config(chi2_cut=cut)
     dbank = P.device_bank(bank.f, bank.q)
     words = P.words_tensor(sample.words)
-    tune = L.make_tune(args.tile, args.chunk, args.wg, args.occ)
+    tune = L.svt_tune_resolve(L.make_tune(args.tile, args.chunk, args.wg, args.occ))
 
     # ---- batched path: resident buffers, graph replay -------------------------------------
     runner = P.BatchRunner(gcfg, dbank, n_words, n_roads, n_combos, kept_cap=0, tune=tune,
@@ -270,8 +325,10 @@ def main():
     k_ms = fused_kernel_ms(runner, K, W)
     alg = algorithmic_bytes(n_combos, n_words, n_roads)
     achieved = alg / (k_ms * 1e-3) / 1e9
+    traffic = recorded_traffic(args.config, n_events)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                    traffic_over_algorithmic=round(traffic / alg, 3) if traffic else None,
                     kernel="k_fused", kernel_ms=round(k_ms, 5), algorithmic_bytes=alg,
                     bytes_per_combination=round(alg / n_combos, 3))
 

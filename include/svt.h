@@ -202,6 +202,11 @@ void svt_set_fused_timing_events(hipEvent_t start, hipEvent_t stop);
 /* Destroy every cached graph (call before freeing buffers a cached graph refers to). */
 void svt_release_graphs(void);
 
+/* Write to `out` the launch parameters svt_process_batch uses for `tune` (NULL or zero fields
+ * take the built-in defaults).  Returns SVT_ERR_ARG when `out` is NULL or the resolved set is
+ * not one the fused kernel is built for, SVT_OK otherwise.  Host memory only. */
+svt_status svt_tune_resolve(const svt_tune *tune, svt_tune *out);
+
 /* Turn an error word into a status (SVT_OK when none) and its index (-1 when none). */
 svt_status svt_error_decode(uint64_t err, int64_t *index);
 

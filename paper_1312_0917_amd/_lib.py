@@ -83,6 +83,7 @@ def load():
                                      _P, _P, _P, _P, _I64, _I32, _P]),
         "svt_set_fused_timing_events": (None, [_P, _P]),
         "svt_release_graphs": (None, []),
+        "svt_tune_resolve": (_I32, [S(svt_tune), S(svt_tune)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -96,7 +97,7 @@ def exported_symbols():
     return ["svt_abi_version", "svt_status_name", "svt_error_decode", "svt_unpack_workspace",
             "svt_combine_workspace", "svt_select_workspace", "svt_batch_workspace", "svt_unpack",
             "svt_combine", "svt_fit", "svt_select", "svt_process_batch",
-            "svt_set_fused_timing_events", "svt_release_graphs"]
+            "svt_set_fused_timing_events", "svt_release_graphs", "svt_tune_resolve"]
 
 
 # ---- marshalling helpers -----------------------------------------------------------------
@@ -123,6 +124,14 @@ def make_config(chi2_cut=256, shift=10, max_hits=8, n_sets=256, n_layers=5) -> s
 
 def make_tune(tile_combos=0, chunk_roads=0, wg_size=0, wgs_per_cu=0) -> svt_tune:
     return svt_tune(tile_combos, chunk_roads, wg_size, wgs_per_cu)
+
+
+def svt_tune_resolve(tune=None) -> svt_tune:
+    """Launch parameters svt_process_batch uses for ``tune`` (defaults filled in)."""
+    out = svt_tune()
+    check(load().svt_tune_resolve(ctypes.byref(tune) if tune is not None else None,
+                                  ctypes.byref(out)), "svt_tune_resolve")
+    return out
 
 
 def roads_struct(d) -> svt_roads:

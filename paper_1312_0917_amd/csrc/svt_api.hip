@@ -129,6 +129,12 @@ extern "C" {
 
 int32_t svt_abi_version(void) { return SVT_ABI_VERSION; }
 
+svt_status svt_tune_resolve(const svt_tune *tune, svt_tune *out) {
+    if (!out) return SVT_ERR_ARG;
+    *out = resolve_tune(tune);
+    return fused_tune_supported(*out) ? SVT_OK : SVT_ERR_ARG;
+}
+
 const char *svt_status_name(svt_status s) {
     switch (s) {
         case SVT_OK: return "SVT_OK";

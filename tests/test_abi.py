@@ -108,3 +108,14 @@ def test_product_path_does_not_import_the_oracle():
     for fn in os.listdir(os.path.join(src_dir, "csrc")):
         text = open(os.path.join(src_dir, "csrc", fn)).read()
         assert "svt_oracle" not in text and "ora_" not in text, fn
+
+
+def test_tune_resolution_fills_defaults_and_rejects_unbuilt_shapes():
+    t = L.svt_tune_resolve()
+    assert (t.tile_combos, t.chunk_roads, t.wg_size, t.wgs_per_cu) == (4096, 64, 256, 3)
+    t = L.svt_tune_resolve(L.make_tune(8192, 0, 512, 0))
+    assert (t.tile_combos, t.chunk_roads, t.wg_size, t.wgs_per_cu) == (8192, 64, 512, 3)
+    for bad in [L.make_tune(wg_size=128), L.make_tune(tile_combos=6000),
+                L.make_tune(chunk_roads=32), L.make_tune(wgs_per_cu=9)]:
+        with pytest.raises(L.SvtError):
+            L.svt_tune_resolve(bad)
