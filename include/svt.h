@@ -45,8 +45,9 @@
  *     many hits in a layer (index = road), then a road tag without a constant set (index =
  *     road), then capacity (index 0 roads, 1 combinations, 2 kept list).  svt_error_decode()
  *     turns the word into an svt_status and index.  After a data error the outputs are
- *     unspecified except the sizes (*d_n_roads, *d_n_combos, *d_n_kept), which are always the
- *     sizes the input needs, so a caller can grow its buffers and retry.
+ *     unspecified except the sizes: *d_n_roads and *d_n_combos are always the sizes the input
+ *     needs (a road with too many hits in a layer counts no combination), so a caller can grow
+ *     its buffers and retry; *d_n_kept is the accepted count when the fit ran, -1 otherwise.
  *   - Kernels never write past a capacity and never read outside the given arrays, whatever
  *     the input words contain.
  *   - Output arrays of the fused pass must be 16-byte aligned (accept: 4-byte aligned).
@@ -178,14 +179,19 @@ svt_status svt_select(const svt_config *cfg, const svt_roads *roads, int64_t n_r
                       int64_t *d_n_kept, uint64_t *d_err, void *d_work, int64_t work_bytes,
                       hipStream_t stream);
 
-/* The whole path in one pass: the words are segmented and sized by a short pre-pass, then a
- * persistent fused kernel takes tiles of tile_combos consecutive combinations, stages the
- * roads' hits and fit-constant partial sums in LDS, fits every combination with integer VALU
- * arithmetic and writes the same records, accept flags, road table and best tracks as stages
- * 1-4 (bit for bit).  The word count is read on the device from *d_n_words, so a captured
- * graph can be replayed for any batch up to word_cap.  flags: SVT_BATCH_GRAPH captures the
- * launch sequence in a HIP graph on first use (keyed by every argument) and replays it
- * afterwards.  kept may be NULL.  Resets *d_err. */
+/* The whole path in one pass (sections II and II-A: unpack, combine, fit, plus the chi-square
+ * selection).  A single-pass pre-pass reads every word once and writes the road table, the
+ * layer-grouped coordinates and each road's combination range (one kernel: decoupled look-back
+ * over blocks of 4096 words).  A persistent fused kernel then takes tiles of tile_combos
+ * consecutive combinations, stages the roads' hits and constants in LDS, fits every combination
+ * with integer VALU arithmetic and writes the same records, accept flags, road table and best
+ * tracks as stages 1-4 (bit for bit).  The word count is read on the device from *d_n_words, so
+ * a captured graph can be replayed for any batch up to word_cap (at most 2^31 - 1 words;
+ * larger capacities are SVT_ERR_ARG, and svt_batch_workspace returns -1 for them).
+ * flags: SVT_BATCH_GRAPH
+ * captures the launch sequence in a HIP graph on first use (keyed by every argument) and
+ * replays it afterwards.  kept may be NULL; with d_n_kept also NULL no accepted count and no
+ * kept list are produced.  Resets *d_err. */
 #define SVT_BATCH_GRAPH 1
 svt_status svt_process_batch(const svt_fconst *bank, const svt_config *cfg, const svt_tune *tune,
                              const uint32_t *words, const int64_t *d_n_words, int64_t word_cap,

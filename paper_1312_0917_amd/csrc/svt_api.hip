@@ -51,12 +51,9 @@ UnpackWs carve_unpack(Carver &c, int64_t n_words) {
 }
 
 struct BatchWs {
-    int64_t *scalars;  // [0] event total
-    uint32_t *tile_counter;
-    int64_t *wb;
+    uint32_t *tickets;  // [0] fused-kernel tiles, [1] pre-pass blocks
+    int64_t *status;    // look-back status words, 2 per word block
     int64_t nb;
-    int64_t *rb;
-    int64_t rbn;
     int32_t *tfr;
     int64_t tiles_cap;
     int64_t *kb;
@@ -66,12 +63,9 @@ struct BatchWs {
 BatchWs carve_batch(Carver &c, int64_t word_cap, int64_t road_cap, int64_t combo_cap,
                     int64_t tile) {
     BatchWs w;
-    w.scalars = c.take<int64_t>(4);
-    w.tile_counter = c.take<uint32_t>(4);
-    w.nb = ceil_div(word_cap > 0 ? word_cap : 1, kSegBlockWords);
-    w.wb = c.take<int64_t>(2 * w.nb);
-    w.rbn = ceil_div(road_cap > 0 ? road_cap : 1, kRoadBlock);
-    w.rb = c.take<int64_t>(w.rbn);
+    w.tickets = c.take<uint32_t>(4);
+    w.nb = ceil_div(word_cap > 0 ? word_cap : 1, kPrepassBlockWords);
+    w.status = c.take<int64_t>(2 * w.nb);
     w.tiles_cap = ceil_div(combo_cap > 0 ? combo_cap : 1, tile) + 1;
     w.tfr = c.take<int32_t>(w.tiles_cap);
     w.kbn = ceil_div(combo_cap > 0 ? combo_cap : 1, kKeptBlock);
@@ -183,7 +177,7 @@ int64_t svt_select_workspace(int64_t n_combos) {
 
 int64_t svt_batch_workspace(int64_t word_cap, int64_t road_cap, int64_t combo_cap,
                             const svt_tune *tune) {
-    if (word_cap < 0 || road_cap < 0 || combo_cap < 0) return -1;
+    if (word_cap < 0 || word_cap > kMaxBatchWords || road_cap < 0 || combo_cap < 0) return -1;
     const svt_tune t = resolve_tune(tune);
     if (!fused_tune_supported(t)) return -1;
     Carver c{nullptr};
@@ -297,19 +291,27 @@ static svt_status batch_sequence(const FusedLaunch &f, const BatchWs &w, int64_t
     const Sizes nw{0, f.d_n_words, word_cap};
     const Sizes nr{0, f.d_n_roads, road_cap};
     const Sizes nc{0, f.d_n_combos, combo_cap};
+    PrepassLaunch p{};
+    p.words = f.words;
+    p.nw = nw;
+    p.cfg = f.cfg;
+    p.roads = f.roads;
+    p.road_cap = road_cap;
+    p.coords = const_cast<int16_t *>(f.coords);
+    p.best = f.best;
+    p.tile_combos = f.tune.tile_combos;
+    p.tile_first_road = w.tfr;
+    p.tiles_cap = w.tiles_cap;
+    p.combo_cap = combo_cap;
+    p.d_n_roads = const_cast<int64_t *>(f.d_n_roads);
+    p.d_n_combos = const_cast<int64_t *>(f.d_n_combos);
+    p.status = w.status;
+    p.nb_cap = w.nb;
+    p.tickets = w.tickets;
+    p.err = f.err;
     uint64_t *err = f.err;
-    SVT_TRY(launch_batch_init(err, w.tile_counter, d_n_kept, stream));
-    SVT_TRY(launch_seg_count(f.words, nw, w.nb, f.cfg.n_layers, w.wb, err, stream));
-    SVT_TRY(launch_scan(w.wb, w.nb, 2, nw, kSegBlockWords, const_cast<int64_t *>(f.d_n_roads),
-                        w.scalars, road_cap, 0, err, false, stream));
-    SVT_TRY(launch_seg_emit(f.words, nw, w.nb, w.wb, f.roads, road_cap, err, stream));
-    SVT_TRY(launch_road_fill(f.words, nw, f.d_n_roads, road_cap, f.roads, f.cfg,
-                             const_cast<int16_t *>(f.coords), nullptr, err, stream));
-    SVT_TRY(launch_combo_count(f.roads, nr, w.rbn, w.rb, err, stream));
-    SVT_TRY(launch_scan(w.rb, 0, 1, nr, kRoadBlock, const_cast<int64_t *>(f.d_n_combos), nullptr,
-                        combo_cap, 1, err, true, stream));
-    SVT_TRY(launch_combo_begin(f.roads, nr, w.rbn, w.rb, f.tune.tile_combos, w.tfr, w.tiles_cap,
-                               &f.best, err, stream));
+    SVT_TRY(launch_batch_reset(p, d_n_kept, stream));
+    SVT_TRY(launch_prepass(p, stream));
     if (d_n_kept) SVT_TRY(launch_zero(w.kb, w.kbn, stream));
     if (timing) SVT_TRY(hipEventRecord(g_ev_start, stream));
     SVT_TRY(launch_fused(f, stream));
@@ -333,7 +335,8 @@ svt_status svt_process_batch(const svt_fconst *bank, const svt_config *cfg, cons
                              void *d_work, int64_t work_bytes, int32_t flags,
                              hipStream_t stream) {
     if (!config_ok(cfg) || !bank || !words || !d_n_words || !roads || !rec || !best ||
-        !d_n_roads || !d_n_combos || !d_err || word_cap < 0 || road_cap < 0 || combo_cap < 0 ||
+        !d_n_roads || !d_n_combos || !d_err || word_cap < 0 || word_cap > kMaxBatchWords ||
+        road_cap < 0 || combo_cap < 0 ||
         kept_cap < 0)
         return SVT_ERR_ARG;
     if (kept && !d_n_kept) return SVT_ERR_ARG;
@@ -371,8 +374,8 @@ svt_status svt_process_batch(const svt_fconst *bank, const svt_config *cfg, cons
     f.accept = accept;
     f.best = *best;
     f.tile_first_road = w.tfr;
-    f.kb_counts = w.kb;
-    f.tile_counter = w.tile_counter;
+    f.kb_counts = d_n_kept ? w.kb : nullptr;
+    f.tile_counter = w.tickets;
     f.err = d_err;
     f.tiles_cap = w.tiles_cap;
     f.road_cap = road_cap;

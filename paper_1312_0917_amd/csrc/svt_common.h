@@ -12,6 +12,7 @@ constexpr int kWaveSize = 64;
 constexpr int kSegThreads = 256;          // threads of the word-segmentation kernels
 constexpr int kSegWordsPerThread = 16;
 constexpr int kSegBlockWords = kSegThreads * kSegWordsPerThread;  // 4096 words per block
+constexpr int kPrepassBlockWords = 2048;  // words per block of the batched single-pass pre-pass
 constexpr int kRoadBlock = 256;           // roads per block in road-table kernels
 constexpr int kKeptBlock = 4096;          // combinations per block of the kept-list compaction
 constexpr int kScanThreads = 1024;        // single-workgroup scan
@@ -25,7 +26,8 @@ __device__ inline uint64_t best_key(int64_t chi2, uint32_t k) {
     if (c > kKeyChiMax) c = kKeyChiMax;
     return (c << kKeyKBits) | k;
 }
-constexpr int kMaxTile = 8192;            // combinations per tile of the fused kernel, at most
+constexpr int kMaxTile = 8192;
+constexpr int64_t kMaxBatchWords = (1ll << 31) - 1;  // batched path: road and event counts fit 31 bits            // combinations per tile of the fused kernel, at most
 
 // ---- error word: (class << 56) | index, smallest wins, all ones = none ------------------
 __device__ inline void report(uint64_t *err, uint32_t cls, uint64_t index) {
@@ -185,7 +187,7 @@ struct FusedLaunch {
     uint8_t *accept;
     svt_best best;
     int32_t *tile_first_road;
-    int64_t *kb_counts;        // per kKeptBlock combinations
+    int64_t *kb_counts;        // per kKeptBlock combinations (null: kept list not wanted)
     uint32_t *tile_counter;
     uint64_t *err;
     int64_t tiles_cap;
@@ -200,8 +202,30 @@ hipError_t launch_zero(int64_t *p, int64_t n, hipStream_t s);
 hipError_t launch_best_finalize(const svt_roads &roads, Sizes n_roads, const svt_fitrec &rec,
                                 Sizes n_combos, const svt_best &best, int64_t cut,
                                 uint64_t *err, bool skip_if_error, hipStream_t s);
-hipError_t launch_batch_init(uint64_t *err, uint32_t *tile_counter, int64_t *d_n_kept,
-                             hipStream_t s);
 bool fused_tune_supported(const svt_tune &t);
+
+// Single-pass unpack + combine of the batched path (decoupled look-back over word blocks).
+struct PrepassLaunch {
+    const uint32_t *words;
+    Sizes nw;                  // device word count, capacity word_cap
+    svt_config cfg;
+    svt_roads roads;
+    int64_t road_cap;
+    int16_t *coords;           // grouped coordinates, word_cap entries
+    svt_best best;             // best keys and n_accept are initialised here
+    int64_t tile_combos;
+    int32_t *tile_first_road;
+    int64_t tiles_cap;
+    int64_t combo_cap;
+    int64_t *d_n_roads;
+    int64_t *d_n_combos;
+    int64_t *status;           // 2 * nb_cap look-back status words
+    int64_t nb_cap;            // ceil(word_cap / kPrepassBlockWords)
+    uint32_t *tickets;         // [0] fused-kernel tiles, [1] pre-pass blocks
+    uint64_t *err;
+};
+// Clears the error word, both tickets, *d_n_kept (nullable) and the status words in use.
+hipError_t launch_batch_reset(const PrepassLaunch &p, int64_t *d_n_kept, hipStream_t s);
+hipError_t launch_prepass(const PrepassLaunch &p, hipStream_t s);
 
 }  // namespace svt

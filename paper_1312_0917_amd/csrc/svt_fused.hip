@@ -412,8 +412,9 @@ __device__ void consume(const FArgs &a, const Stage &S, int ctid, int nthreads) 
             acc_bits |= ((valid_bits >> e) & 1u) && vchi[e] <= a.cut ? (1u << e) : 0u;
         const int64_t gi = tile_start + rel0;
         if (acc_bits) {  // rare: reduce inside the group, then one global atomic per road
-            atomicAdd(a.kb_counts + gi / kKeptBlock,
-                      static_cast<unsigned long long>(__popc(acc_bits)));
+            if (a.kb_counts)
+                atomicAdd(a.kb_counts + gi / kKeptBlock,
+                          static_cast<unsigned long long>(__popc(acc_bits)));
             if (one_road) {
                 unsigned long long kmin = ~0ull;
 #pragma unroll
@@ -535,12 +536,6 @@ hipError_t launch_fused_t(const FArgs &a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-__global__ void k_batch_init(uint64_t *err, uint32_t *tile_counter, int64_t *d_n_kept) {
-    *err = SVT_NO_ERROR;
-    *tile_counter = 0;
-    if (d_n_kept) *d_n_kept = 0;
-}
-
 __global__ void k_zero(int64_t *p, int64_t n) {
     for (int64_t i = gtid(); i < n; i += gstride()) p[i] = 0;
 }
@@ -562,12 +557,6 @@ hipError_t launch_fused(const FusedLaunch &f, hipStream_t s) {
     if (f.tune.wg_size == 256) return launch_fused_t<256>(a, grid, s);
     if (f.tune.wg_size == 512) return launch_fused_t<512>(a, grid, s);
     return hipErrorInvalidValue;
-}
-
-hipError_t launch_batch_init(uint64_t *err, uint32_t *tile_counter, int64_t *d_n_kept,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_init, dim3(1), dim3(1), 0, s, err, tile_counter, d_n_kept);
-    return hipGetLastError();
 }
 
 hipError_t launch_zero(int64_t *p, int64_t n, hipStream_t s) {

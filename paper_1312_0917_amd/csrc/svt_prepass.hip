@@ -1,0 +1,432 @@
+// Single-pass unpack + combine of the batched path: one kernel reads every hit word once and
+// writes the whole road table (event, set, hit_begin, nhits, ncombo, combo_begin), the
+// layer-grouped coordinates, the first road of every fit tile and the initial best-track keys.
+//
+// Section II-A of the paper: the serial code first unpacks the input and fills its data
+// structures, then counts the hit combinations of every road.  Both need running counts over
+// the whole stream (which road and event a word belongs to, where a road's combinations start);
+// here they come from one decoupled look-back over blocks of 2048 words instead of separate
+// count / scan / emit launches.
+//
+// Ownership: a block owns the roads that *start* among its 2048 words.  A road may run past the
+// block's last word; the block stages 64 more words, which covers every legal road (at most
+// n_layers * max_hits = 40 words), and a road still running after them is reported as a hit-count
+// error (some layer must then hold more than max_hits hits).
+//
+// Everything a block needs from its own words (road list, hits per layer, combinations,
+// grouped coordinates) is computed before it looks back, so the only wait is one look-back.
+// Blocks take ordered tickets, so a block only ever waits on blocks that started before it.
+// Two 64-bit status words per block carry the running counts -- roads and events packed in one
+// (31 bits each: a batch holds fewer than 2^31 words), combinations in the other: the top two
+// bits say "aggregate of this block" or "inclusive prefix up to this block", the rest hold the
+// value.  The status words are cleared by the batch-reset kernel before every pass.  Waits are
+// bounded: a look-back that does not finish within the bound reports an internal error and
+// still publishes, instead of spinning forever.
+#include "svt_common.h"
+
+namespace svt {
+namespace {
+
+constexpr int kPT = 256;                  // threads per block
+constexpr int kPB = kPrepassBlockWords;   // 2048 words per block
+constexpr int kPW = kPB / kPT;            // 8 words per thread
+constexpr int kTail = 64;                 // words staged past the block's own
+constexpr int kOff = 4;                   // sw[kOff - 1] = word before the block (16-byte aligned body)
+constexpr uint64_t kStAgg = 1ull << 62;
+constexpr uint64_t kStIncl = 2ull << 62;
+constexpr uint64_t kStMask = 3ull << 62;
+constexpr int kSpinLimit = 1 << 20;
+constexpr int kLookWindows = 8;           // predecessors read per round: 64 per window
+
+__device__ inline void status_publish(int64_t *p, uint64_t v) {
+    __hip_atomic_store(reinterpret_cast<uint64_t *>(p), v, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline uint64_t status_read(int64_t *p) {
+    return __hip_atomic_load(reinterpret_cast<uint64_t *>(p), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefixes over blocks 0..b-1 of two status columns at once (col0[i], col1[i] =
+// column 0 and 1 of block i).  Publishes this block's aggregates first and its inclusive
+// prefixes once known.  Executed by one whole wave; the results are valid in every lane.  One
+// round reads kLookWindows * 64 predecessors of both columns (lane i of window k inspects block
+// top - 64 k - i, so position 0 is the nearest predecessor); each column sums its values up to
+// its nearest block that already has an inclusive value.  Values are opaque sums: counts packed
+// in one word add field by field as long as no field overflows.
+__device__ void look_back2(int64_t *col0, int64_t *col1, int64_t b, uint64_t agg0,
+                           uint64_t agg1, uint64_t *err, uint64_t &ex0, uint64_t &ex1) {
+    const int lane = lane_id();
+    ex0 = 0;
+    ex1 = 0;
+    if (b == 0) {
+        if (lane == 0) {
+            status_publish(col0, kStIncl | agg0);
+            status_publish(col1, kStIncl | agg1);
+        }
+        return;
+    }
+    if (lane == 0) {
+        status_publish(col0 + b, kStAgg | agg0);
+        status_publish(col1 + b, kStAgg | agg1);
+    }
+    bool done0 = false, done1 = false;
+    int64_t top = b - 1;
+    int spins = 0;
+    while (!(done0 && done1)) {
+        uint64_t v0[kLookWindows], v1[kLookWindows];
+#pragma unroll
+        for (int k = 0; k < kLookWindows; ++k) {
+            const int64_t idx = top - 64 * k - lane;
+            v0[k] = (idx >= 0 && !done0) ? status_read(col0 + idx) : kStIncl;
+            v1[k] = (idx >= 0 && !done1) ? status_read(col1 + idx) : kStIncl;
+        }
+        int f0 = 64 * kLookWindows, f1 = 64 * kLookWindows;  // nearest inclusive positions
+#pragma unroll
+        for (int k = kLookWindows - 1; k >= 0; --k) {
+            const uint64_t m0 = __ballot((v0[k] & kStMask) == kStIncl);
+            const uint64_t m1 = __ballot((v1[k] & kStMask) == kStIncl);
+            if (m0) f0 = 64 * k + __builtin_ctzll(m0);
+            if (m1) f1 = 64 * k + __builtin_ctzll(m1);
+        }
+        bool wait = false;
+#pragma unroll
+        for (int k = 0; k < kLookWindows; ++k) {
+            const int pos = 64 * k + lane;
+            wait |= __ballot(((v0[k] & kStMask) == 0 && pos <= f0) ||
+                             ((v1[k] & kStMask) == 0 && pos <= f1)) != 0;
+        }
+        if (wait) {  // a block at or before a nearest inclusive one has not published yet
+            if (++spins > kSpinLimit) {  // never expected: give up, but still publish so
+                if (lane == 0)            // that the blocks after this one finish too
+                    report(err, SVT_ERRCLASS_INDEX, static_cast<uint64_t>(b));
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        uint64_t m0 = 0, m1 = 0;
+#pragma unroll
+        for (int k = 0; k < kLookWindows; ++k) {
+            const int pos = 64 * k + lane;
+            if (!done0 && pos <= f0) m0 += v0[k] & ~kStMask;
+            if (!done1 && pos <= f1) m1 += v1[k] & ~kStMask;
+        }
+        ex0 += wave_sum(m0);
+        ex1 += wave_sum(m1);
+        done0 |= f0 < 64 * kLookWindows;
+        done1 |= f1 < 64 * kLookWindows;
+        top -= 64 * kLookWindows;
+    }
+    if (lane == 0) {
+        status_publish(col0 + b, kStIncl | (ex0 + agg0));
+        status_publish(col1 + b, kStIncl | (ex1 + agg1));
+    }
+}
+
+struct PArgs {
+    const uint32_t *words;
+    Sizes nw;
+    svt_config cfg;
+    svt_roads roads;
+    int64_t road_cap;
+    int16_t *coords;
+    svt_best best;
+    int64_t tile_combos;
+    int32_t *tile_first_road;
+    int64_t tiles_cap;
+    int64_t combo_cap;
+    int64_t *d_n_roads;
+    int64_t *d_n_combos;
+    int64_t *status;  // [2][nb_cap]: roads | events << 31, combinations
+    int64_t nb_cap;
+    uint32_t *ticket;
+    uint64_t *err;
+};
+
+__device__ inline int64_t combos_of(uint32_t packed) {
+    int64_t c = 1;
+#pragma unroll
+    for (int l = 0; l < SVT_N_LAYERS; ++l) c *= nh_of(packed, l);
+    return c;
+}
+
+// Per owned road, in LDS: s_road[rl] = first local word (12 bits) | events started in the block
+// up to that word (12 bits) << 12; s_info[rl] = hits per layer (4 bits each) | too-many-hits
+// << 20 | no-constant-set << 21.
+constexpr uint32_t kInfoOver = 1u << 20;
+constexpr uint32_t kInfoSet = 1u << 21;
+
+__global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
+    __shared__ __align__(16) uint32_t sw[kOff + kPB + kTail];  // word base + j at sw[kOff + j]
+    __shared__ int16_t sc[kPB + kTail];   // grouped coordinates, same local positions
+    __shared__ uint32_t s_road[kPB + 1];  // [n_owned] holds the end of the last owned road
+    __shared__ uint32_t s_info[kPB];
+    __shared__ int64_t tmp[kPT / kWaveSize + 1];
+    __shared__ int64_t s_pre[3];
+    __shared__ int64_t s_blk;
+    __shared__ int32_t s_tail_end;
+
+    const int tid = threadIdx.x;
+    if (tid == 0) s_blk = atomicAdd(a.ticket, 1u);
+    __syncthreads();
+    const int64_t b = s_blk;
+    const int64_t n = load_size(a.nw);
+    const int64_t nb = (n + kPB - 1) / kPB;
+    if (b == 0 && tid == 0 && a.nw.dev && *a.nw.dev > a.nw.cap)
+        report(a.err, SVT_ERRCLASS_CAPACITY, 3);
+    if (b >= nb) {
+        if (b == 0 && tid == 0) {  // empty batch
+            *a.d_n_roads = 0;
+            *a.d_n_combos = 0;
+        }
+        return;
+    }
+
+    // ---- stage the block's words, 64 more, and the word before ------------------------------
+    const int64_t base = b * kPB;
+    const int nloc = static_cast<int>(n - base < kPB + kTail ? n - base : kPB + kTail);
+    const int nown = nloc < kPB ? nloc : kPB;
+    const int j0 = tid * kPW;
+    const bool aligned16 = (reinterpret_cast<uintptr_t>(a.words) & 15) == 0;
+    if (aligned16 && j0 + kPW <= nown) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(a.words + base + j0);
+        uint4 *q = reinterpret_cast<uint4 *>(sw + kOff + j0);
+#pragma unroll
+        for (int v = 0; v < kPW / 4; ++v) q[v] = p[v];
+    } else {
+#pragma unroll
+        for (int e = 0; e < kPW; ++e)
+            sw[kOff + j0 + e] = (j0 + e < nloc) ? a.words[base + j0 + e] : 0u;
+    }
+    if (tid < kTail) sw[kOff + kPB + tid] = (kPB + tid < nloc) ? a.words[base + kPB + tid] : 0u;
+    if (tid == 0) sw[kOff - 1] = base > 0 ? a.words[base - 1] : 0u;
+    __syncthreads();
+
+    // ---- road and event starts of this thread's words ---------------------------------------
+    uint32_t rmask = 0, emask = 0;
+    int nr = 0, ne = 0;
+    int64_t bad = -1;
+#pragma unroll
+    for (int e = 0; e < kPW; ++e) {
+        const int j = j0 + e;
+        if (j < nown) {
+            const uint32_t x = sw[kOff + j];
+            const uint32_t px = sw[kOff + j - 1];
+            const bool first = (base + j == 0);
+            const bool r = first || w_tags(x) != w_tags(px);
+            const bool v = first || w_etag(x) != w_etag(px);
+            rmask |= (r ? 1u : 0u) << e;
+            emask |= (v ? 1u : 0u) << e;
+            nr += r;
+            ne += v;
+            if (bad < 0 && static_cast<int32_t>(w_layer(x)) >= a.cfg.n_layers) bad = base + j;
+        }
+    }
+    if (bad >= 0) report(a.err, SVT_ERRCLASS_LAYER, static_cast<uint64_t>(bad));
+    if (tid < kWaveSize) {
+        // end of the last owned road: the first road start among the staged words past the
+        // block, else the end of the staged words (the end of the input, or a road longer than
+        // any legal one)
+        const int j = kPB + tid;
+        const bool start = j < nloc && w_tags(sw[kOff + j]) != w_tags(sw[kOff + j - 1]);
+        const uint64_t m = __ballot(start);
+        if (tid == 0) s_tail_end = nloc <= kPB ? nloc : (m ? kPB + __builtin_ctzll(m) : nloc);
+    }
+    int64_t tre;  // roads and events of the block, scanned together (each at most 2048)
+    const int64_t rel0 = block_excl_scan<int64_t, kPT>(static_cast<int64_t>(nr) |
+                                                       (static_cast<int64_t>(ne) << 32), tmp, tre);
+    const int rl0 = static_cast<int>(rel0 & 0xFFFFFFFF), el0 = static_cast<int>(rel0 >> 32);
+    const int64_t tr = tre & 0xFFFFFFFF, te = tre >> 32;
+    const int nroads = static_cast<int>(tr);
+
+    // ---- list of owned roads ------------------------------------------------------------------
+    {
+        int rl = rl0;
+        int ev = el0;  // events started in the block up to the current word
+#pragma unroll
+        for (int e = 0; e < kPW; ++e) {
+            ev += (emask >> e) & 1u;
+            if ((rmask >> e) & 1u) s_road[rl++] = static_cast<uint32_t>(j0 + e) |
+                                                  (static_cast<uint32_t>(ev) << 12);
+        }
+        if (tid == 0) s_road[nroads] = static_cast<uint32_t>(s_tail_end);
+    }
+    __syncthreads();
+
+    // ---- one road per thread: hits per layer, checks, grouped coordinates -------------------
+    const int max_len = a.cfg.n_layers * a.cfg.max_hits;
+    int64_t csum = 0;
+    for (int rl = tid; rl < nroads; rl += kPT) {
+        const int j = s_road[rl] & 0xFFF;
+        const int len = static_cast<int>(s_road[rl + 1] & 0xFFF) - j;
+        bool over = len > max_len;
+        uint64_t cnt = 0;  // 8 bits per layer
+        if (!over) {
+            for (int i0 = 0; i0 < len; i0 += 8) {
+                uint32_t x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = i0 + u < len ? sw[kOff + j + i0 + u] : 0xE000u;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const uint32_t l = w_layer(x[u]);  // 7 for the padding
+                    if (l < SVT_N_LAYERS) cnt += 1ull << (8 * l);
+                }
+            }
+        }
+        uint32_t packed = 0;
+        uint32_t off[SVT_N_LAYERS];
+        uint32_t run = 0;
+#pragma unroll
+        for (int l = 0; l < SVT_N_LAYERS; ++l) {
+            const uint32_t c = static_cast<uint32_t>((cnt >> (8 * l)) & 0xFF);
+            over |= c > static_cast<uint32_t>(a.cfg.max_hits);
+            packed |= (c & 0xFu) << (4 * l);
+            off[l] = run;
+            run += c;
+        }
+        if (!over) {
+            for (int i0 = 0; i0 < len; i0 += 8) {
+                uint32_t x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = i0 + u < len ? sw[kOff + j + i0 + u] : 0xE000u;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const uint32_t l = w_layer(x[u]);
+                    if (l >= SVT_N_LAYERS) continue;
+                    uint32_t o = 0;
+#pragma unroll
+                    for (int k = 0; k < SVT_N_LAYERS; ++k)
+                        if (static_cast<uint32_t>(k) == l) { o = off[k]; off[k] = o + 1; }
+                    sc[j + o] = static_cast<int16_t>(w_coord(x[u]));
+                }
+            }
+            csum += combos_of(packed);
+        }
+        const bool noset = w_rtag(sw[kOff + j]) >= static_cast<uint32_t>(a.cfg.n_sets);
+        s_info[rl] = packed | (over ? kInfoOver : 0u) | (noset ? kInfoSet : 0u);
+    }
+    const int64_t tc = block_sum<int64_t, kPT>(csum, tmp);
+
+    // ---- running counts of the blocks before this one (roads and events share a word: both
+    // stay below 2^31) ---------------------------------------------------------------------------
+    if (tid < kWaveSize) {
+        uint64_t p0, p1;
+        look_back2(a.status, a.status + a.nb_cap, b,
+                   static_cast<uint64_t>(tr) | (static_cast<uint64_t>(te) << 31),
+                   static_cast<uint64_t>(tc), a.err, p0, p1);
+        if (tid == 0) {
+            s_pre[0] = static_cast<int64_t>(p0 & 0x7FFFFFFFull);
+            s_pre[1] = static_cast<int64_t>(p0 >> 31);
+            s_pre[2] = static_cast<int64_t>(p1);
+        }
+    }
+    __syncthreads();
+    const int64_t R0 = s_pre[0], E0 = s_pre[1];
+
+    // ---- road table, combo_begin (scan over the road list), tiles, best keys ----------------
+    {
+        int64_t carry = s_pre[2];
+        const int64_t T = a.tile_combos;
+        uint64_t *keys = reinterpret_cast<uint64_t *>(a.best.chi2);
+        for (int q0 = 0; q0 < nroads; q0 += kPT) {
+            const int rl = q0 + tid;
+            const bool mine = rl < nroads;
+            const uint32_t info = mine ? s_info[rl] : kInfoOver;
+            const int64_t c = (info & kInfoOver) ? 0 : combos_of(info);
+            int64_t tot;
+            const int64_t cb = carry + block_excl_scan<int64_t, kPT>(c, tmp, tot);
+            carry += tot;
+            if (!mine) continue;
+            const int64_t r = R0 + rl;
+            if (info & kInfoOver) report(a.err, SVT_ERRCLASS_HITS, static_cast<uint64_t>(r));
+            if (info & kInfoSet) report(a.err, SVT_ERRCLASS_SET, static_cast<uint64_t>(r));
+            if (r >= a.road_cap) continue;
+            const uint32_t rd = s_road[rl];
+            const int j = rd & 0xFFF;
+            a.roads.event[r] = static_cast<int32_t>(E0 + (rd >> 12) - 1);
+            a.roads.set[r] = static_cast<int32_t>(w_rtag(sw[kOff + j]));
+            a.roads.hit_begin[r] = base + j;
+            a.roads.nhits[r] = info & 0xFFFFFu;
+            a.roads.ncombo[r] = static_cast<int32_t>(c);
+            a.roads.combo_begin[r] = cb;
+            keys[r] = UINT64_MAX;
+            a.best.n_accept[r] = 0;
+            if (T > 0 && c > 0) {
+                for (int64_t t = (cb + T - 1) / T; t * T < cb + c; ++t)
+                    if (t < a.tiles_cap) a.tile_first_road[t] = static_cast<int32_t>(r);
+            }
+        }
+    }
+
+    // ---- grouped coordinates of the owned roads: contiguous, coalesced ----------------------
+    if (nroads > 0) {
+        const int lo = s_road[0] & 0xFFF, hi = s_road[nroads] & 0xFFF;
+        for (int j = lo + tid; j < hi; j += kPT) a.coords[base + j] = sc[j];
+    }
+    if (b == nb - 1 && tid == 0) {
+        const int64_t n_roads = R0 + tr;
+        const int64_t n_combos = s_pre[2] + tc;
+        *a.d_n_roads = n_roads;
+        *a.d_n_combos = n_combos;
+        if (n_roads > a.road_cap) report(a.err, SVT_ERRCLASS_CAPACITY, 0);
+        if (n_combos > a.combo_cap) report(a.err, SVT_ERRCLASS_CAPACITY, 1);
+    }
+}
+
+// Clears the error word, the two work tickets, the kept count and the look-back status words
+// of the blocks this pass will use.
+__global__ void k_batch_reset(uint64_t *err, uint32_t *tickets, int64_t *d_n_kept,
+                              int64_t *status, int64_t nb_cap, Sizes nw) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *err = SVT_NO_ERROR;
+        tickets[0] = 0;
+        tickets[1] = 0;
+        if (d_n_kept) *d_n_kept = 0;
+    }
+    const int64_t n = load_size(nw);
+    int64_t nb = (n + kPB - 1) / kPB;
+    if (nb > nb_cap) nb = nb_cap;
+    for (int64_t i = gtid(); i < nb; i += gstride()) {
+        status[i] = 0;
+        status[nb_cap + i] = 0;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_prepass(const PrepassLaunch &p, hipStream_t s) {
+    PArgs a;
+    a.words = p.words;
+    a.nw = p.nw;
+    a.cfg = p.cfg;
+    a.roads = p.roads;
+    a.road_cap = p.road_cap;
+    a.coords = p.coords;
+    a.best = p.best;
+    a.tile_combos = p.tile_combos;
+    a.tile_first_road = p.tile_first_road;
+    a.tiles_cap = p.tiles_cap;
+    a.combo_cap = p.combo_cap;
+    a.d_n_roads = p.d_n_roads;
+    a.d_n_combos = p.d_n_combos;
+    a.status = p.status;
+    a.nb_cap = p.nb_cap;
+    a.ticket = p.tickets + 1;
+    a.err = p.err;
+    const int64_t grid = p.nb_cap > 0 ? p.nb_cap : 1;
+    hipLaunchKernelGGL(k_prepass, dim3(static_cast<unsigned>(grid)), dim3(kPT), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(const PrepassLaunch &p, int64_t *d_n_kept, hipStream_t s) {
+    int64_t blocks = (p.nb_cap + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_batch_reset, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                       p.err, p.tickets, d_n_kept, p.status, p.nb_cap, p.nw);
+    return hipGetLastError();
+}
+
+}  // namespace svt

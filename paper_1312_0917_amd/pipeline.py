@@ -233,14 +233,17 @@ class BatchRunner:
         st = L.svt_process_batch(self.bank, self.cfg, self.tune, self.words, self.d_n[0:1],
                                  self.word_cap, self.roads, self.road_cap, self.rec, self.accept,
                                  self.combo_cap, self.best, self.kept, self.kept_cap,
-                                 self.d_n[1:2], self.d_n[2:3], self.d_n[3:4], self.d_err,
+                                 self.d_n[1:2], self.d_n[2:3],
+                                 self.d_n[3:4] if self.kept_cap > 0 else None, self.d_err,
                                  self.work, L.SVT_BATCH_GRAPH if self.graph else 0, s)
         L.check(st, "svt_process_batch")
         return self
 
     def sizes(self):
         v = self.d_n.cpu().tolist()
-        return dict(n_words=v[0], n_roads=v[1], n_combos=v[2], n_kept=v[3])
+        # the accepted count is only produced when a kept list is wanted
+        return dict(n_words=v[0], n_roads=v[1], n_combos=v[2],
+                    n_kept=v[3] if self.kept_cap > 0 else None)
 
     def error(self):
         err = _err_value(self.d_err)

@@ -67,6 +67,9 @@ def test_workspace_sizes_are_aligned_and_monotone():
     assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, L.make_tune(1000, 64, 256, 4)) == -1
     assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, L.make_tune(16384, 64, 256, 4)) == -1
     assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, L.make_tune(8192, 32, 256, 4)) == -1
+    # the batched path holds at most 2^31 - 1 words per batch
+    assert L.svt_batch_workspace((1 << 31) - 1, 1 << 16, 1 << 22, t) > 0
+    assert L.svt_batch_workspace(1 << 31, 1 << 16, 1 << 22, t) == -1
 
 
 def test_host_argument_checks_reject_without_launching():
