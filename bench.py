@@ -224,6 +224,23 @@ def measure_serving(bank, n_events, warmup_events, rate_hz, n_slots, max_events,
                 slots=n_slots, max_events_per_batch=max_events, batched=batched, plain=plain)
 
 
+def measure_transfer(bank, tune, reps, workers):
+    """Packet latency with pageable, pinned and mapped input (serving-shaped events)."""
+    import numpy as np
+    from paper_1312_0917_amd import _lib as L
+    from paper_1312_0917_amd import pipeline as P
+    from paper_1312_0917_amd import synth, transfer
+
+    sample = synth.make_sample("c4", n_events=10000, bank=bank, workers=workers)
+    combos = np.prod(sample.road_nhits.astype(np.int64), axis=1)
+    pts = transfer.study(sample.words, sample.event_word_begin, sample.road_event, combos,
+                         L.make_config(chi2_cut=synth.config_chi2_cut("c4")),
+                         P.device_bank(bank.f, bank.q), tune=tune, reps=reps, log=log)
+    return dict(workload="c4-shaped events (16-256 roads, 1-4 hits per layer), packets of "
+                         "600 kB to 64 MB; per point the mean of %d packets" % reps,
+                points=[p.as_dict() for p in pts])
+
+
 def run_cpu_baseline(sample, bank, cfg, seconds):
     import oracle
 
@@ -257,6 +274,8 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=5000)
     ap.add_argument("--serve-rate", type=float, default=100e3)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--transfer-reps", type=int, default=10,
+                    help="packets per point of the transfer study; 0 skips it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB three times (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -365,6 +384,11 @@ def main():
         serving = measure_serving(bank, args.serve_events, args.serve_warmup, args.serve_rate,
                                   args.serve_slots, 256, tune, args.workers)
 
+    transfer = None
+    if args.transfer_reps > 0:
+        log("transfer study")
+        transfer = measure_transfer(bank, tune, args.transfer_reps, args.workers)
+
     large = None
     if args.large_events > 0:
         L.svt_release_graphs()
@@ -393,7 +417,7 @@ def main():
                               wg_size=t.wg_size, wgs_per_cu=t.wgs_per_cu),
                     device=dev_name),
         roofline=roofline, cpu_baseline=cpu, plain=plain, uneven_autotuned=uneven,
-        serving=serving, max_scale=large)
+        serving=serving, transfer=transfer, max_scale=large)
     print(json.dumps(out), flush=True)
 
 

@@ -205,6 +205,12 @@ svt_status svt_process_batch(const svt_fconst *bank, const svt_config *cfg, cons
  * right before and `stop` right after the fused kernel, on the call's stream (for timing). */
 void svt_set_fused_timing_events(hipEvent_t start, hipEvent_t stop);
 
+/* Device-side address of page-locked host memory (from hipHostMalloc, e.g. a pinned torch
+ * tensor), so kernels can read it in place over the bus ("zero-copy" input).  Returns
+ * SVT_ERR_ARG for NULL arguments and SVT_ERR_HIP when the runtime does not know the pointer.
+ * Host call, no allocation. */
+svt_status svt_mapped_pointer(void *host, void **dev);
+
 /* Destroy every cached graph (call before freeing buffers a cached graph refers to). */
 void svt_release_graphs(void);
 

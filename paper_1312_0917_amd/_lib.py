@@ -84,6 +84,7 @@ def load():
         "svt_set_fused_timing_events": (None, [_P, _P]),
         "svt_release_graphs": (None, []),
         "svt_tune_resolve": (_I32, [S(svt_tune), S(svt_tune)]),
+        "svt_mapped_pointer": (_I32, [_P, S(_P)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -97,7 +98,8 @@ def exported_symbols():
     return ["svt_abi_version", "svt_status_name", "svt_error_decode", "svt_unpack_workspace",
             "svt_combine_workspace", "svt_select_workspace", "svt_batch_workspace", "svt_unpack",
             "svt_combine", "svt_fit", "svt_select", "svt_process_batch",
-            "svt_set_fused_timing_events", "svt_release_graphs", "svt_tune_resolve"]
+            "svt_set_fused_timing_events", "svt_release_graphs", "svt_tune_resolve",
+            "svt_mapped_pointer"]
 
 
 # ---- marshalling helpers -----------------------------------------------------------------
@@ -249,3 +251,10 @@ def svt_set_fused_timing_events(start, stop):
 
 def svt_release_graphs():
     load().svt_release_graphs()
+
+
+def svt_mapped_pointer(host) -> int:
+    """Device address of page-locked host memory (a pinned tensor or an address)."""
+    dev = _P()
+    check(load().svt_mapped_pointer(_ptr(host), ctypes.byref(dev)), "svt_mapped_pointer")
+    return int(dev.value)

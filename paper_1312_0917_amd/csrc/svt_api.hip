@@ -123,6 +123,12 @@ extern "C" {
 
 int32_t svt_abi_version(void) { return SVT_ABI_VERSION; }
 
+svt_status svt_mapped_pointer(void *host, void **dev) {
+    if (!host || !dev) return SVT_ERR_ARG;
+    *dev = nullptr;
+    return hipHostGetDevicePointer(dev, host, 0) == hipSuccess && *dev ? SVT_OK : SVT_ERR_HIP;
+}
+
 svt_status svt_tune_resolve(const svt_tune *tune, svt_tune *out) {
     if (!out) return SVT_ERR_ARG;
     *out = resolve_tune(tune);
@@ -317,7 +323,7 @@ static svt_status batch_sequence(const FusedLaunch &f, const BatchWs &w, int64_t
     SVT_TRY(launch_fused(f, stream));
     if (timing) SVT_TRY(hipEventRecord(g_ev_stop, stream));
     SVT_TRY(launch_best_finalize(f.roads, nr, f.rec, nc, f.best, f.cfg.chi2_cut, err, true,
-                                 stream));
+                                 f.bank, f.coords, f.cfg.shift, stream));
     if (d_n_kept) {
         SVT_TRY(launch_scan(w.kb, 0, 1, nc, kKeptBlock, d_n_kept, nullptr, kept ? kept_cap : -1,
                             2, err, true, stream));

@@ -198,10 +198,12 @@ struct FusedLaunch {
 hipError_t launch_fused(const FusedLaunch &f, hipStream_t s);
 hipError_t launch_zero(int64_t *p, int64_t n, hipStream_t s);
 // Per road: turn the best-track key left in best.chi2 into (k, chi2, p0..p2), reading the
-// parameters from the records (exact rescan of a road whose key saturated).
+// parameters from the records, or fitting them again from the grouped coordinates when bank
+// and coords are given (exact rescan of the records for a road whose key saturated).
 hipError_t launch_best_finalize(const svt_roads &roads, Sizes n_roads, const svt_fitrec &rec,
                                 Sizes n_combos, const svt_best &best, int64_t cut,
-                                uint64_t *err, bool skip_if_error, hipStream_t s);
+                                uint64_t *err, bool skip_if_error, const svt_fconst *bank,
+                                const int16_t *coords, int32_t shift, hipStream_t s);
 bool fused_tune_supported(const svt_tune &t);
 
 // Single-pass unpack + combine of the batched path (decoupled look-back over word blocks).

@@ -29,6 +29,8 @@ constexpr int kChunk = 64;             // roads staged per chunk: one loader lan
 constexpr int kWordCap = 2048;         // coordinates staged per chunk (a road has at most 40)
 constexpr int kTabCap = 2048;          // coordinate-pair table entries per chunk (<= 136/road)
 constexpr int kMapCap = kMaxTile / 4;  // groups of 4 combinations in a tile
+constexpr int64_t kListedMaxMean = 48;  // mean combinations per road below which road-spanning
+                                        // groups get a pass of their own (consume_listed)
 
 struct FArgs {
     const svt_fconst *bank;
@@ -143,13 +145,14 @@ __device__ __forceinline__ Fit fit_combo(const RoadMeta &m, const RoadConst &c, 
 struct Stage {
     alignas(16) int16_t G[kWordCap + 32];  // layer-grouped coordinates (16-byte copy slack)
     int32_t XT[kTabCap];                   // coordinate-pair tables
-    uint8_t M[kMapCap];                    // group of 4 combinations -> staged road
+    uint8_t M[kMapCap];                    // group of 4 combinations -> road of its first one
+    uint16_t X[kChunk];                    // groups that span a road boundary (from g_lo)
     RoadMeta meta[kChunk];
     RoadConst rc[kChunk];
     int32_t rb[kChunk];                    // road begin relative to the tile start
     int64_t tile_start;
     int64_t r_first;                       // global index of staged road 0
-    int32_t nr, cs, ce, g_lo, g_hi, done;
+    int32_t nr, cs, ce, g_lo, g_hi, nx, done;
 };
 
 struct Loader {
@@ -328,6 +331,18 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
             if (ghi > g_hi) ghi = g_hi;
             for (int32_t g = glo; g < ghi; ++g) S.M[g - g_lo] = static_cast<uint8_t>(lane);
         }
+        // groups that span a road boundary: a road with combinations starts inside the group
+        // (not at a multiple of 4) after the chunk's first combination; one entry per group
+        {
+            const int32_t g = rb >> 2;
+            const bool cut = fits && C > 0 && (rb & 3) != 0 && rb > cs && rb < ce;
+            const bool pcut = __shfl_up(cut ? 1 : 0, 1) != 0 && lane > 0;
+            const int32_t pg = __shfl_up(g, 1);
+            const bool head = cut && !(pcut && pg == g);
+            const uint64_t hm = __ballot(head);
+            if (head) S.X[__popcll(hm & ((1ull << lane) - 1))] = static_cast<uint16_t>(g - g_lo);
+            if (lane == 0) S.nx = __popcll(hm);
+        }
         if (lane == 0) {
             S.tile_start = L.tile_start;
             S.r_first = r_first;
@@ -342,8 +357,160 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
     }
 }
 
-// Compute waves: fit every combination of a staged chunk that lies inside its tile.
-__device__ void consume(const FArgs &a, const Stage &S, int ctid, int nthreads) {
+// Write the records of one group of 4 consecutive combinations (global index gi of slot 0):
+// one 16-byte store per array when all four slots are written, else one store per slot.
+__device__ __forceinline__ void store_group(const FArgs &a, int64_t gi, uint32_t slots,
+                                            uint32_t acc_bits, const int32_t *vp0,
+                                            const int32_t *vp1, const int32_t *vp2,
+                                            const int32_t *vc0, const int32_t *vc1,
+                                            const int32_t *vc2, const int64_t *vchi) {
+    if (slots == 0xF) {
+        *reinterpret_cast<int4 *>(a.rec.p0 + gi) = make_int4(vp0[0], vp0[1], vp0[2], vp0[3]);
+        *reinterpret_cast<int4 *>(a.rec.p1 + gi) = make_int4(vp1[0], vp1[1], vp1[2], vp1[3]);
+        *reinterpret_cast<int4 *>(a.rec.p2 + gi) = make_int4(vp2[0], vp2[1], vp2[2], vp2[3]);
+        longlong2 *c2p = reinterpret_cast<longlong2 *>(a.rec.chi2 + gi);
+        c2p[0] = make_longlong2(vchi[0], vchi[1]);
+        c2p[1] = make_longlong2(vchi[2], vchi[3]);
+        if (a.rec.c0) *reinterpret_cast<int4 *>(a.rec.c0 + gi) = make_int4(vc0[0], vc0[1], vc0[2], vc0[3]);
+        if (a.rec.c1) *reinterpret_cast<int4 *>(a.rec.c1 + gi) = make_int4(vc1[0], vc1[1], vc1[2], vc1[3]);
+        if (a.rec.c2) *reinterpret_cast<int4 *>(a.rec.c2 + gi) = make_int4(vc2[0], vc2[1], vc2[2], vc2[3]);
+        const uint32_t accw = (acc_bits & 1u) | ((acc_bits & 2u) << 7) |
+                              ((acc_bits & 4u) << 14) | ((acc_bits & 8u) << 21);
+        *reinterpret_cast<uint32_t *>(a.accept + gi) = accw;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (slots & (1u << e)) {
+                a.rec.p0[gi + e] = vp0[e];
+                a.rec.p1[gi + e] = vp1[e];
+                a.rec.p2[gi + e] = vp2[e];
+                a.rec.chi2[gi + e] = vchi[e];
+                if (a.rec.c0) a.rec.c0[gi + e] = vc0[e];
+                if (a.rec.c1) a.rec.c1[gi + e] = vc1[e];
+                if (a.rec.c2) a.rec.c2[gi + e] = vc2[e];
+                a.accept[gi + e] = (acc_bits >> e) & 1u;
+            }
+        }
+    }
+}
+
+// A group whose valid slots all lie in staged road ri: four fits with one road's constants
+// (slots outside `slots` compute a harmless dummy, k = 0, and are not written).
+__device__ __forceinline__ void fit_group(const FArgs &a, const Stage &S, int ri, int32_t rel0,
+                                          uint32_t slots, int64_t tile_start, int64_t r_first) {
+    const RoadMeta m = S.meta[ri];
+    const RoadConst c = S.rc[ri];
+    const int32_t rbase = S.rb[ri];
+    int32_t vp0[4], vp1[4], vp2[4], vc0[4], vc1[4], vc2[4];
+    int64_t vchi[4];
+    int32_t kk[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int32_t k = ((slots >> e) & 1u) ? rel0 + e - rbase : 0;
+        const Fit f = fit_combo(m, c, static_cast<uint32_t>(k), S.XT, a.shift);
+        vp0[e] = f.v[0]; vp1[e] = f.v[1]; vp2[e] = f.v[2];
+        vc0[e] = f.v[3]; vc1[e] = f.v[4]; vc2[e] = f.v[5];
+        vchi[e] = f.chi2;
+        kk[e] = k;
+    }
+    uint32_t acc_bits = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        acc_bits |= ((slots >> e) & 1u) && vchi[e] <= a.cut ? (1u << e) : 0u;
+    const int64_t gi = tile_start + rel0;
+    if (acc_bits) {  // rare: one global atomic pair per road and group
+        unsigned long long *keys = reinterpret_cast<unsigned long long *>(a.best.chi2);
+        if (a.kb_counts)
+            atomicAdd(a.kb_counts + gi / kKeptBlock,
+                      static_cast<unsigned long long>(__popc(acc_bits)));
+        unsigned long long kmin = ~0ull;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if ((acc_bits >> e) & 1u) {
+                const unsigned long long kv = best_key(vchi[e], static_cast<uint32_t>(kk[e]));
+                kmin = kv < kmin ? kv : kmin;
+            }
+        atomicMin(keys + r_first + ri, kmin);
+        atomicAdd(a.best.n_accept + r_first + ri, __popc(acc_bits));
+    }
+    store_group(a, gi, slots, acc_bits, vp0, vp1, vp2, vc0, vc1, vc2, vchi);
+}
+
+// A group that spans road boundaries: each slot is fitted with the constants of its own road
+// (road ri holds the first valid slot; later roads follow in staging order) and written on its
+// own.  Rare (at most one group per road), so it is kept small rather than fast.
+__device__ void fit_group_split(const FArgs &a, const Stage &S, int ri, int32_t rel0,
+                                uint32_t slots, int64_t tile_start, int64_t r_first) {
+    const int nr = S.nr;
+    const int64_t gi = tile_start + rel0;
+    unsigned long long *keys = reinterpret_cast<unsigned long long *>(a.best.chi2);
+    int r = ri;
+#pragma unroll 1
+    for (int e = 0; e < 4; ++e) {
+        if (!((slots >> e) & 1u)) continue;
+        const int32_t ci = rel0 + e;
+        while (r + 1 < nr && ci >= S.rb[r] + S.meta[r].C) ++r;  // skips empty roads
+        const int32_t k = ci - S.rb[r];
+        const Fit f = fit_combo(S.meta[r], S.rc[r], static_cast<uint32_t>(k), S.XT, a.shift);
+        const bool acc = f.chi2 <= a.cut;
+        a.rec.p0[gi + e] = f.v[0];
+        a.rec.p1[gi + e] = f.v[1];
+        a.rec.p2[gi + e] = f.v[2];
+        a.rec.chi2[gi + e] = f.chi2;
+        if (a.rec.c0) a.rec.c0[gi + e] = f.v[3];
+        if (a.rec.c1) a.rec.c1[gi + e] = f.v[4];
+        if (a.rec.c2) a.rec.c2[gi + e] = f.v[5];
+        a.accept[gi + e] = acc ? 1 : 0;
+        if (acc) {
+            if (a.kb_counts) atomicAdd(a.kb_counts + (gi + e) / kKeptBlock, 1ull);
+            atomicMin(keys + r_first + r,
+                      static_cast<unsigned long long>(best_key(f.chi2, static_cast<uint32_t>(k))));
+            atomicAdd(a.best.n_accept + r_first + r, 1);
+        }
+    }
+}
+
+// Compute waves, for batches of small roads: fit every combination of a staged chunk that lies
+// inside its tile.  A lane takes a group of 4 consecutive combinations.  Groups inside one road take the uniform path
+// (one road's constants, full 16-byte stores); the few groups that span a road boundary are
+// listed by the loader and handled as extra items of the same loop, each slot with its own
+// road, so that every group is written by exactly one lane.
+__device__ void consume_listed(const FArgs &a, const Stage &S, int ctid, int nthreads) {
+    const int32_t cs = S.cs, ce = S.ce, g_lo = S.g_lo, g_hi = S.g_hi;
+    const int64_t tile_start = S.tile_start, r_first = S.r_first;
+    const int32_t ng = g_hi - g_lo;
+    for (int32_t it = ctid; it < ng; it += nthreads) {
+        const int32_t g = g_lo + it;
+        const int32_t rel0 = g << 2;
+        const int ri = S.M[it];
+        const int32_t end = S.rb[ri] + S.meta[ri].C;  // end of road ri
+        uint32_t valid = 0, in_ri = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            valid |= (rel0 + e >= cs && rel0 + e < ce) ? (1u << e) : 0u;
+            in_ri |= (rel0 + e < end) ? (1u << e) : 0u;
+        }
+        if (valid & ~in_ri) continue;  // spans a road boundary: a listed group
+        fit_group(a, S, ri, rel0, valid, tile_start, r_first);
+    }
+    // listed groups continue the same round-robin over the compute threads
+    const int32_t items = ng + S.nx;
+    for (int32_t it = ctid + ((ng - ctid + nthreads - 1) / nthreads) * nthreads; it < items;
+         it += nthreads) {
+        const int32_t off = S.X[it - ng];
+        const int32_t rel0 = (g_lo + off) << 2;
+        uint32_t valid = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) valid |= (rel0 + e >= cs && rel0 + e < ce) ? (1u << e) : 0u;
+        fit_group_split(a, S, S.M[off], rel0, valid, tile_start, r_first);
+    }
+}
+
+// Compute waves, for batches of large roads: each lane fits its group of 4 consecutive
+// combinations itself, a group that spans a road boundary slot by slot.  Large roads make such
+// groups rare inside a lane's work, and keeping them in the same pass adds no extra round to
+// the chunk; small roads make them frequent, and consume_listed() is then faster.
+__device__ void consume_inline(const FArgs &a, const Stage &S, int ctid, int nthreads) {
     const int nr = S.nr;
     const int32_t cs = S.cs, ce = S.ce, g_lo = S.g_lo, g_hi = S.g_hi;
     const int64_t tile_start = S.tile_start, r_first = S.r_first;
@@ -468,7 +635,7 @@ __device__ void consume(const FArgs &a, const Stage &S, int ctid, int nthreads) 
 }
 
 template <int WG>
-__global__ __launch_bounds__(WG) void k_fused(FArgs a) {
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG == 256 ? 3 : 2))) void k_fused(FArgs a) {
     static_assert(WG > kWaveSize, "one loader wave plus compute waves");
     __shared__ Stage S[2];
 
@@ -481,6 +648,8 @@ __global__ __launch_bounds__(WG) void k_fused(FArgs a) {
     if (n_tiles > a.tiles_cap) return;
     const int wave = threadIdx.x / kWaveSize;
     const uint32_t qlmask = (1u << a.shift) - 1u;
+    // road-boundary handling for this batch, from its mean combinations per road
+    const bool listed = n_combos < kListedMaxMean * n_roads;
 
     Loader L;
     L.t = blockIdx.x;
@@ -499,8 +668,10 @@ __global__ __launch_bounds__(WG) void k_fused(FArgs a) {
     while (!S[cur].done) {
         if (wave == 0)
             produce(a, S[cur ^ 1], L, n_roads, n_combos, n_tiles, T, qlmask);
+        else if (listed)
+            consume_listed(a, S[cur], static_cast<int>(threadIdx.x) - kWaveSize, WG - kWaveSize);
         else
-            consume(a, S[cur], static_cast<int>(threadIdx.x) - kWaveSize, WG - kWaveSize);
+            consume_inline(a, S[cur], static_cast<int>(threadIdx.x) - kWaveSize, WG - kWaveSize);
         __syncthreads();
         cur ^= 1;
     }

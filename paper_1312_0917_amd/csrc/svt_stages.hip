@@ -414,9 +414,44 @@ __global__ __launch_bounds__(kSegThreads) void k_select_mark(svt_config cfg, svt
     }
 }
 
+// Parameters of combination k of road r, fitted again from the grouped coordinates and the
+// road's constant set (the same integer arithmetic as the records, so the same values).
+__device__ inline void refit_params(const svt_fconst *__restrict__ bank,
+                                    const int16_t *__restrict__ coords, int32_t shift,
+                                    uint32_t nh, int64_t hb, int32_t set, uint32_t k,
+                                    int32_t *p) {
+    uint32_t h[SVT_N_LAYERS];
+#pragma unroll
+    for (int l = SVT_N_LAYERS - 1; l >= 0; --l) {  // layer 0 most significant
+        const uint32_t nl = nh_of(nh, l);
+        h[l] = k % nl;
+        k /= nl;
+    }
+    int64_t off = hb;
+    int32_t x[SVT_N_LAYERS];
+#pragma unroll
+    for (int l = 0; l < SVT_N_LAYERS; ++l) {
+        x[l] = coords[off + h[l]];
+        off += nh_of(nh, l);
+    }
+    const svt_fconst &F = bank[set];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        int64_t acc = F.q[j];
+#pragma unroll
+        for (int l = 0; l < SVT_N_LAYERS; ++l)
+            acc += static_cast<int64_t>(F.f[j][l]) * static_cast<int64_t>(x[l]);
+        p[j] = static_cast<int32_t>(acc >> shift);
+    }
+}
+
+// With bank and coords (batched path), the best track's parameters are fitted again from its
+// hits instead of gathered from the three record arrays: one coordinate line per road instead
+// of three scattered reads.
 __global__ void k_best_finalize(svt_roads roads, Sizes n_roads_s, svt_fitrec rec,
                                 Sizes n_combos_s, svt_best best, int64_t cut, uint64_t *err,
-                                int32_t skip_if_error) {
+                                int32_t skip_if_error, const svt_fconst *bank,
+                                const int16_t *coords, int32_t shift) {
     if (skip_if_error && has_error(err)) return;
     const int64_t n_roads = load_size(n_roads_s);
     const int64_t n_combos = load_size(n_combos_s);
@@ -458,10 +493,19 @@ __global__ void k_best_finalize(svt_roads roads, Sizes n_roads_s, svt_fitrec rec
             const int64_t g = cb + k;
             best.k[r] = k;
             best.chi2[r] = static_cast<int64_t>(key >> kKeyKBits);
-            const bool in = g >= 0 && g < n_combos;
-            best.p0[r] = in ? rec.p0[g] : INT32_MIN;
-            best.p1[r] = in ? rec.p1[g] : INT32_MIN;
-            best.p2[r] = in ? rec.p2[g] : INT32_MIN;
+            const bool in = g >= 0 && g < n_combos && k < nc;
+            if (bank && coords && in) {
+                int32_t p[3];
+                refit_params(bank, coords, shift, roads.nhits[r], roads.hit_begin[r],
+                             roads.set[r], static_cast<uint32_t>(k), p);
+                best.p0[r] = p[0];
+                best.p1[r] = p[1];
+                best.p2[r] = p[2];
+            } else {
+                best.p0[r] = in ? rec.p0[g] : INT32_MIN;
+                best.p1[r] = in ? rec.p1[g] : INT32_MIN;
+                best.p2[r] = in ? rec.p2[g] : INT32_MIN;
+            }
         }
     }
 }
@@ -601,16 +645,17 @@ hipError_t launch_select(const svt_config &cfg, const svt_roads &roads, int64_t 
     if (n_roads > 0)
         return launch_best_finalize(roads, Sizes{n_roads, nullptr, n_roads}, rec,
                                     Sizes{n_combos, nullptr, n_combos}, best, cfg.chi2_cut, err,
-                                    false, s);
+                                    false, nullptr, nullptr, 0, s);
     return hipGetLastError();
 }
 
 hipError_t launch_best_finalize(const svt_roads &roads, Sizes n_roads, const svt_fitrec &rec,
                                 Sizes n_combos, const svt_best &best, int64_t cut,
-                                uint64_t *err, bool skip_if_error, hipStream_t s) {
+                                uint64_t *err, bool skip_if_error, const svt_fconst *bank,
+                                const int16_t *coords, int32_t shift, hipStream_t s) {
     const int64_t g = clamp_grid((n_roads.cap + 255) / 256, 1 << 14);
     hipLaunchKernelGGL(k_best_finalize, dim3(g), dim3(256), 0, s, roads, n_roads, rec, n_combos,
-                       best, cut, err, static_cast<int32_t>(skip_if_error));
+                       best, cut, err, static_cast<int32_t>(skip_if_error), bank, coords, shift);
     return hipGetLastError();
 }
 

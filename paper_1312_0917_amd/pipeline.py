@@ -228,9 +228,13 @@ class BatchRunner:
         self.n_words = n
         return self
 
-    def run(self, stream=None):
+    def run(self, stream=None, words=None):
+        """One pass over the batch.  ``words``: another word buffer the kernels can read
+        (a device tensor, or the device address of mapped host memory), default the
+        resident one."""
         s = stream if stream is not None else self.stream
-        st = L.svt_process_batch(self.bank, self.cfg, self.tune, self.words, self.d_n[0:1],
+        src = self.words if words is None else words
+        st = L.svt_process_batch(self.bank, self.cfg, self.tune, src, self.d_n[0:1],
                                  self.word_cap, self.roads, self.road_cap, self.rec, self.accept,
                                  self.combo_cap, self.best, self.kept, self.kept_cap,
                                  self.d_n[1:2], self.d_n[2:3],

@@ -93,3 +93,13 @@ def test_latency_includes_waiting_for_a_slot(stream_and_bank):
     assert stats.latency_s.max() > 5e-3 * 3
     summ = stats.summary()
     assert summ["p99_us"] >= summ["p50_us"] > 0 and summ["events"] == st.n_events
+
+
+def test_packet_sizes_pick_leading_events():
+    from paper_1312_0917_amd import transfer
+    ewb = np.array([0, 100, 250, 400, 1000], dtype=np.int64)  # words per event: 100,150,150,600
+    assert transfer.packet_events(ewb, 4) == 1
+    assert transfer.packet_events(ewb, 400) == 1        # 100 words = 400 bytes
+    assert transfer.packet_events(ewb, 404) == 2
+    assert transfer.packet_events(ewb, 1600) == 3
+    assert transfer.packet_events(ewb, 10**9) == 4      # everything
