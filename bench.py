@@ -23,6 +23,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# integer VALU lane-operations per second: 256 CUs x 64 lanes per clock x 2.4 GHz
+INT_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# algorithmic integer operations of one fit as the method states it: 6 x 5 multiply-adds,
+# 6 offset adds, 6 shifts, 3 squares, 2 adds, 1 compare
+INT_OPS_PER_COMBO = 30 + 6 + 6 + 3 + 2 + 1
 METRIC = "fitted combinations/s and p50/p99 event latency (µs), batched vs plain"
 
 
@@ -241,6 +246,41 @@ def measure_transfer(bank, tune, reps, workers):
                 points=[p.as_dict() for p in pts])
 
 
+def measure_kept_only(gcfg, dbank, words, n_words, n_roads, n_combos, tune, steps, warmup,
+                      graph):
+    """The same batch in kept-only mode: accept flags, kept list and best tracks, no records."""
+    import torch
+    from paper_1312_0917_amd import _lib as L
+    from paper_1312_0917_amd import pipeline as P
+
+    kept_cap = n_combos // 16 + 4096
+    runner = P.BatchRunner(gcfg, dbank, n_words, n_roads, n_combos, kept_cap=kept_cap, tune=tune,
+                           graph=graph, with_c=False, kept_only=True)
+    runner.load(words)
+    for _ in range(warmup):
+        runner.run()
+    torch.cuda.synchronize()
+    assert runner.error() == (0, -1), runner.error()
+    n_kept = runner.sizes()["n_kept"]
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        runner.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    k_ms = fused_kernel_ms(runner, steps, warmup)
+    ops = INT_OPS_PER_COMBO * n_combos
+    achieved = ops / (k_ms * 1e-3) / 1e12
+    L.svt_release_graphs()
+    del runner
+    torch.cuda.empty_cache()
+    return dict(value=n_combos / dt, unit="fitted combinations/s", ms_per_step=round(dt * 1e3, 5),
+                kept=n_kept,
+                roofline=dict(bound="alu", achieved=round(achieved, 3), peak=round(INT_PEAK_TOPS, 1),
+                              unit="Tops/s", frac=round(achieved / INT_PEAK_TOPS, 4),
+                              kernel="k_fused", kernel_ms=round(k_ms, 5),
+                              ops_per_combination=INT_OPS_PER_COMBO))
+
+
 def run_cpu_baseline(sample, bank, cfg, seconds):
     import oracle
 
@@ -274,6 +314,7 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=5000)
     ap.add_argument("--serve-rate", type=float, default=100e3)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--no-kept-only", action="store_true", help="skip the kept-only mode run")
     ap.add_argument("--transfer-reps", type=int, default=10,
                     help="packets per point of the transfer study; 0 skips it")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -351,6 +392,14 @@ def main():
                     kernel="k_fused", kernel_ms=round(k_ms, 5), algorithmic_bytes=alg,
                     bytes_per_combination=round(alg / n_combos, 3))
 
+    # ---- kept-only mode: no per-combination records ----------------------------------------
+    kept_only = None
+    if not args.no_kept_only:
+        log("kept-only mode")
+        L.svt_release_graphs()
+        kept_only = measure_kept_only(gcfg, dbank, words, n_words, n_roads, n_combos, tune, K, W,
+                                      not args.no_graph)
+
     # ---- plain path: one launch per stage, host syncs to size each stage ------------------
     plain = None
     if not args.no_plain:
@@ -416,7 +465,8 @@ def main():
                     tune=dict(tile_combos=t.tile_combos, chunk_roads=t.chunk_roads,
                               wg_size=t.wg_size, wgs_per_cu=t.wgs_per_cu),
                     device=dev_name),
-        roofline=roofline, cpu_baseline=cpu, plain=plain, uneven_autotuned=uneven,
+        roofline=roofline, cpu_baseline=cpu, kept_only=kept_only, plain=plain,
+        uneven_autotuned=uneven,
         serving=serving, transfer=transfer, max_scale=large)
     print(json.dumps(out), flush=True)
 

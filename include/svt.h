@@ -193,6 +193,14 @@ svt_status svt_select(const svt_config *cfg, const svt_roads *roads, int64_t n_r
  * replays it afterwards.  kept may be NULL; with d_n_kept also NULL no accepted count and no
  * kept list are produced.  Resets *d_err. */
 #define SVT_BATCH_GRAPH 1
+/* flags: SVT_BATCH_KEPT_ONLY writes no per-combination records -- the output a trigger
+ * consumes (section II: the fit's chi-square decides which tracks are kept).  accept[] is still
+ * written per combination and best[] per road; kept (required, with d_n_kept) receives the
+ * ascending indices of the accepted combinations and rec their fit values, compacted: entry i
+ * of rec->p0..p2, chi2 (and c0..c2 when non-NULL) belongs to combination kept[i], kept_cap
+ * entries each.  The values are fitted again for the accepted combinations only, with the
+ * same integer arithmetic, so they equal the records of the default mode bit for bit. */
+#define SVT_BATCH_KEPT_ONLY 2
 svt_status svt_process_batch(const svt_fconst *bank, const svt_config *cfg, const svt_tune *tune,
                              const uint32_t *words, const int64_t *d_n_words, int64_t word_cap,
                              const svt_roads *roads, int64_t road_cap, const svt_fitrec *rec,

@@ -18,6 +18,7 @@ SVT_OK, SVT_ERR_ARG, SVT_ERR_LAYER, SVT_ERR_HITS = 0, -1, -2, -3
 SVT_ERR_CAPACITY, SVT_ERR_HIP, SVT_ERR_SET = -4, -5, -6
 SVT_NO_ERROR = (1 << 64) - 1
 SVT_BATCH_GRAPH = 1
+SVT_BATCH_KEPT_ONLY = 2
 
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64

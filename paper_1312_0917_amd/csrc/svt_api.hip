@@ -322,12 +322,18 @@ static svt_status batch_sequence(const FusedLaunch &f, const BatchWs &w, int64_t
     if (timing) SVT_TRY(hipEventRecord(g_ev_start, stream));
     SVT_TRY(launch_fused(f, stream));
     if (timing) SVT_TRY(hipEventRecord(g_ev_stop, stream));
-    SVT_TRY(launch_best_finalize(f.roads, nr, f.rec, nc, f.best, f.cfg.chi2_cut, err, true,
-                                 f.bank, f.coords, f.cfg.shift, stream));
+    SVT_TRY(launch_best_finalize(f.roads, nr, f.kept_only ? svt_fitrec{} : f.rec, nc, f.best,
+                                 f.cfg.chi2_cut, err, true, f.bank, f.coords, f.cfg.shift,
+                                 stream));
     if (d_n_kept) {
         SVT_TRY(launch_scan(w.kb, 0, 1, nc, kKeptBlock, d_n_kept, nullptr, kept ? kept_cap : -1,
                             2, err, true, stream));
-        if (kept) SVT_TRY(launch_kept_write(f.accept, nc, w.kbn, w.kb, kept, kept_cap, err, stream));
+        if (kept && f.kept_only)
+            SVT_TRY(launch_kept_refit(f.accept, nc, nr, w.kbn, w.kb, f.roads, w.tfr,
+                                      f.tune.tile_combos, f.bank, f.coords, f.cfg.shift, kept,
+                                      f.rec, kept_cap, err, stream));
+        else if (kept)
+            SVT_TRY(launch_kept_write(f.accept, nc, w.kbn, w.kb, kept, kept_cap, err, stream));
     }
     return SVT_OK;
 }
@@ -346,6 +352,8 @@ svt_status svt_process_batch(const svt_fconst *bank, const svt_config *cfg, cons
         kept_cap < 0)
         return SVT_ERR_ARG;
     if (kept && !d_n_kept) return SVT_ERR_ARG;
+    const bool kept_only = (flags & SVT_BATCH_KEPT_ONLY) != 0;
+    if (kept_only && (!kept || !d_n_kept)) return SVT_ERR_ARG;
     if (!roads->event || !roads->set || !roads->hit_begin || !roads->nhits ||
         !roads->combo_begin || !roads->ncombo)
         return SVT_ERR_ARG;
@@ -387,6 +395,7 @@ svt_status svt_process_batch(const svt_fconst *bank, const svt_config *cfg, cons
     f.road_cap = road_cap;
     f.combo_cap = combo_cap;
     f.num_cus = cus;
+    f.kept_only = kept_only;
 
     if (!(flags & SVT_BATCH_GRAPH)) {
         const bool timing = g_ev_start && g_ev_stop;
@@ -410,7 +419,7 @@ svt_status svt_process_batch(const svt_fconst *bank, const svt_config *cfg, cons
                     static_cast<uint64_t>(cfg->chi2_cut), static_cast<uint64_t>(cfg->max_hits),
                     static_cast<uint64_t>(cfg->n_sets), static_cast<uint64_t>(t.tile_combos),
                     static_cast<uint64_t>(t.chunk_roads), static_cast<uint64_t>(t.wg_size),
-                    static_cast<uint64_t>(t.wgs_per_cu)};
+                    static_cast<uint64_t>(t.wgs_per_cu), static_cast<uint64_t>(flags)};
     std::lock_guard<std::mutex> lock(g_graph_mu);
     auto &cache = graph_cache();
     auto it = cache.find(key);

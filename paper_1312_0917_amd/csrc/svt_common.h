@@ -172,6 +172,15 @@ hipError_t launch_select(const svt_config &cfg, const svt_roads &roads, int64_t 
 hipError_t launch_kept_write(const uint8_t *accept, Sizes n_combos, int64_t grid_blocks,
                              const int64_t *kb_prefix, int64_t *kept, int64_t kept_cap,
                              uint64_t *err, hipStream_t s);
+// Kept-only mode: the ascending indices of accepted combinations into kept[] and their fit
+// values, compacted, into rec (entry i for combination kept[i]), fitted again from the grouped
+// coordinates and the constant bank.  tile_first_road / tile_combos locate each block's roads.
+hipError_t launch_kept_refit(const uint8_t *accept, Sizes n_combos, Sizes n_roads,
+                             int64_t grid_blocks, const int64_t *kb_prefix, const svt_roads &roads,
+                             const int32_t *tile_first_road, int64_t tile_combos,
+                             const svt_fconst *bank, const int16_t *coords, int32_t shift,
+                             int64_t *kept, const svt_fitrec &rec, int64_t kept_cap,
+                             uint64_t *err, hipStream_t s);
 
 struct FusedLaunch {
     const svt_fconst *bank;
@@ -194,6 +203,7 @@ struct FusedLaunch {
     int64_t road_cap;
     int64_t combo_cap;
     int num_cus;
+    bool kept_only;            // no per-combination records (accept flags still written)
 };
 hipError_t launch_fused(const FusedLaunch &f, hipStream_t s);
 hipError_t launch_zero(int64_t *p, int64_t n, hipStream_t s);

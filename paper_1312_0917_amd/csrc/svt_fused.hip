@@ -52,6 +52,7 @@ struct FArgs {
     int64_t tiles_cap;
     int64_t road_cap;
     int64_t combo_cap;
+    int32_t records;        // 0: kept-only mode, no per-combination records
 };
 
 // Per-road indexing data of the current chunk, in LDS (32 bytes).
@@ -153,6 +154,7 @@ struct Stage {
     int64_t tile_start;
     int64_t r_first;                       // global index of staged road 0
     int32_t nr, cs, ce, g_lo, g_hi, nx, done;
+    int32_t work[2];                       // next unclaimed group / listed group (LDS atomics)
 };
 
 struct Loader {
@@ -352,9 +354,20 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
             S.g_lo = g_lo;
             S.g_hi = g_hi;
             S.done = 0;
+            S.work[0] = 0;
+            S.work[1] = 0;
         }
         return;
     }
+}
+
+// First of the next 64 work items of a staged chunk for the calling wave (wave-uniform); lane i
+// takes item base + i.  Waves claim work as they become free, the loader wave included once it
+// has staged the next chunk, so no wave waits at the chunk barrier for a slower one.
+__device__ __forceinline__ int32_t claim64(int32_t *counter) {
+    int32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(counter, kWaveSize);
+    return __shfl(base, 0);
 }
 
 // Write the records of one group of 4 consecutive combinations (global index gi of slot 0):
@@ -365,15 +378,17 @@ __device__ __forceinline__ void store_group(const FArgs &a, int64_t gi, uint32_t
                                             const int32_t *vc0, const int32_t *vc1,
                                             const int32_t *vc2, const int64_t *vchi) {
     if (slots == 0xF) {
-        *reinterpret_cast<int4 *>(a.rec.p0 + gi) = make_int4(vp0[0], vp0[1], vp0[2], vp0[3]);
-        *reinterpret_cast<int4 *>(a.rec.p1 + gi) = make_int4(vp1[0], vp1[1], vp1[2], vp1[3]);
-        *reinterpret_cast<int4 *>(a.rec.p2 + gi) = make_int4(vp2[0], vp2[1], vp2[2], vp2[3]);
-        longlong2 *c2p = reinterpret_cast<longlong2 *>(a.rec.chi2 + gi);
-        c2p[0] = make_longlong2(vchi[0], vchi[1]);
-        c2p[1] = make_longlong2(vchi[2], vchi[3]);
-        if (a.rec.c0) *reinterpret_cast<int4 *>(a.rec.c0 + gi) = make_int4(vc0[0], vc0[1], vc0[2], vc0[3]);
-        if (a.rec.c1) *reinterpret_cast<int4 *>(a.rec.c1 + gi) = make_int4(vc1[0], vc1[1], vc1[2], vc1[3]);
-        if (a.rec.c2) *reinterpret_cast<int4 *>(a.rec.c2 + gi) = make_int4(vc2[0], vc2[1], vc2[2], vc2[3]);
+        if (a.records) {  // per-combination records (not in kept-only mode)
+            *reinterpret_cast<int4 *>(a.rec.p0 + gi) = make_int4(vp0[0], vp0[1], vp0[2], vp0[3]);
+            *reinterpret_cast<int4 *>(a.rec.p1 + gi) = make_int4(vp1[0], vp1[1], vp1[2], vp1[3]);
+            *reinterpret_cast<int4 *>(a.rec.p2 + gi) = make_int4(vp2[0], vp2[1], vp2[2], vp2[3]);
+            longlong2 *c2p = reinterpret_cast<longlong2 *>(a.rec.chi2 + gi);
+            c2p[0] = make_longlong2(vchi[0], vchi[1]);
+            c2p[1] = make_longlong2(vchi[2], vchi[3]);
+            if (a.rec.c0) *reinterpret_cast<int4 *>(a.rec.c0 + gi) = make_int4(vc0[0], vc0[1], vc0[2], vc0[3]);
+            if (a.rec.c1) *reinterpret_cast<int4 *>(a.rec.c1 + gi) = make_int4(vc1[0], vc1[1], vc1[2], vc1[3]);
+            if (a.rec.c2) *reinterpret_cast<int4 *>(a.rec.c2 + gi) = make_int4(vc2[0], vc2[1], vc2[2], vc2[3]);
+        }
         const uint32_t accw = (acc_bits & 1u) | ((acc_bits & 2u) << 7) |
                               ((acc_bits & 4u) << 14) | ((acc_bits & 8u) << 21);
         *reinterpret_cast<uint32_t *>(a.accept + gi) = accw;
@@ -381,13 +396,15 @@ __device__ __forceinline__ void store_group(const FArgs &a, int64_t gi, uint32_t
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             if (slots & (1u << e)) {
-                a.rec.p0[gi + e] = vp0[e];
-                a.rec.p1[gi + e] = vp1[e];
-                a.rec.p2[gi + e] = vp2[e];
-                a.rec.chi2[gi + e] = vchi[e];
-                if (a.rec.c0) a.rec.c0[gi + e] = vc0[e];
-                if (a.rec.c1) a.rec.c1[gi + e] = vc1[e];
-                if (a.rec.c2) a.rec.c2[gi + e] = vc2[e];
+                if (a.records) {
+                    a.rec.p0[gi + e] = vp0[e];
+                    a.rec.p1[gi + e] = vp1[e];
+                    a.rec.p2[gi + e] = vp2[e];
+                    a.rec.chi2[gi + e] = vchi[e];
+                    if (a.rec.c0) a.rec.c0[gi + e] = vc0[e];
+                    if (a.rec.c1) a.rec.c1[gi + e] = vc1[e];
+                    if (a.rec.c2) a.rec.c2[gi + e] = vc2[e];
+                }
                 a.accept[gi + e] = (acc_bits >> e) & 1u;
             }
         }
@@ -453,13 +470,15 @@ __device__ void fit_group_split(const FArgs &a, const Stage &S, int ri, int32_t 
         const int32_t k = ci - S.rb[r];
         const Fit f = fit_combo(S.meta[r], S.rc[r], static_cast<uint32_t>(k), S.XT, a.shift);
         const bool acc = f.chi2 <= a.cut;
-        a.rec.p0[gi + e] = f.v[0];
-        a.rec.p1[gi + e] = f.v[1];
-        a.rec.p2[gi + e] = f.v[2];
-        a.rec.chi2[gi + e] = f.chi2;
-        if (a.rec.c0) a.rec.c0[gi + e] = f.v[3];
-        if (a.rec.c1) a.rec.c1[gi + e] = f.v[4];
-        if (a.rec.c2) a.rec.c2[gi + e] = f.v[5];
+        if (a.records) {
+            a.rec.p0[gi + e] = f.v[0];
+            a.rec.p1[gi + e] = f.v[1];
+            a.rec.p2[gi + e] = f.v[2];
+            a.rec.chi2[gi + e] = f.chi2;
+            if (a.rec.c0) a.rec.c0[gi + e] = f.v[3];
+            if (a.rec.c1) a.rec.c1[gi + e] = f.v[4];
+            if (a.rec.c2) a.rec.c2[gi + e] = f.v[5];
+        }
         a.accept[gi + e] = acc ? 1 : 0;
         if (acc) {
             if (a.kb_counts) atomicAdd(a.kb_counts + (gi + e) / kKeptBlock, 1ull);
@@ -471,38 +490,48 @@ __device__ void fit_group_split(const FArgs &a, const Stage &S, int ri, int32_t 
 }
 
 // Compute waves, for batches of small roads: fit every combination of a staged chunk that lies
-// inside its tile.  A lane takes a group of 4 consecutive combinations.  Groups inside one road take the uniform path
-// (one road's constants, full 16-byte stores); the few groups that span a road boundary are
-// listed by the loader and handled as extra items of the same loop, each slot with its own
-// road, so that every group is written by exactly one lane.
-__device__ void consume_listed(const FArgs &a, const Stage &S, int ctid, int nthreads) {
+// inside its tile.  A lane takes a group of 4 consecutive combinations.  Groups inside one
+// road take the uniform path (one road's constants, full 16-byte stores); the few groups that
+// span a road boundary are listed by the loader and fitted after the others, each slot with its
+// own road, so that every group is written by exactly one lane.
+__device__ void consume_listed(const FArgs &a, Stage &S) {
     const int32_t cs = S.cs, ce = S.ce, g_lo = S.g_lo, g_hi = S.g_hi;
     const int64_t tile_start = S.tile_start, r_first = S.r_first;
     const int32_t ng = g_hi - g_lo;
-    for (int32_t it = ctid; it < ng; it += nthreads) {
-        const int32_t g = g_lo + it;
-        const int32_t rel0 = g << 2;
-        const int ri = S.M[it];
-        const int32_t end = S.rb[ri] + S.meta[ri].C;  // end of road ri
-        uint32_t valid = 0, in_ri = 0;
+    const int lane = lane_id();
+    while (true) {
+        const int32_t base = claim64(&S.work[0]);
+        if (base >= ng) break;
+        const int32_t it = base + lane;
+        if (it < ng) {
+            const int32_t g = g_lo + it;
+            const int32_t rel0 = g << 2;
+            const int ri = S.M[it];
+            const int32_t end = S.rb[ri] + S.meta[ri].C;  // end of road ri
+            uint32_t valid = 0, in_ri = 0;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            valid |= (rel0 + e >= cs && rel0 + e < ce) ? (1u << e) : 0u;
-            in_ri |= (rel0 + e < end) ? (1u << e) : 0u;
+            for (int e = 0; e < 4; ++e) {
+                valid |= (rel0 + e >= cs && rel0 + e < ce) ? (1u << e) : 0u;
+                in_ri |= (rel0 + e < end) ? (1u << e) : 0u;
+            }
+            // a group spanning a road boundary is a listed group, fitted below
+            if (!(valid & ~in_ri)) fit_group(a, S, ri, rel0, valid, tile_start, r_first);
         }
-        if (valid & ~in_ri) continue;  // spans a road boundary: a listed group
-        fit_group(a, S, ri, rel0, valid, tile_start, r_first);
     }
-    // listed groups continue the same round-robin over the compute threads
-    const int32_t items = ng + S.nx;
-    for (int32_t it = ctid + ((ng - ctid + nthreads - 1) / nthreads) * nthreads; it < items;
-         it += nthreads) {
-        const int32_t off = S.X[it - ng];
-        const int32_t rel0 = (g_lo + off) << 2;
-        uint32_t valid = 0;
+    const int32_t nx = S.nx;
+    while (true) {
+        const int32_t base = claim64(&S.work[1]);
+        if (base >= nx) break;
+        const int32_t j = base + lane;
+        if (j < nx) {
+            const int32_t off = S.X[j];
+            const int32_t rel0 = (g_lo + off) << 2;
+            uint32_t valid = 0;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) valid |= (rel0 + e >= cs && rel0 + e < ce) ? (1u << e) : 0u;
-        fit_group_split(a, S, S.M[off], rel0, valid, tile_start, r_first);
+            for (int e = 0; e < 4; ++e)
+                valid |= (rel0 + e >= cs && rel0 + e < ce) ? (1u << e) : 0u;
+            fit_group_split(a, S, S.M[off], rel0, valid, tile_start, r_first);
+        }
     }
 }
 
@@ -510,12 +539,17 @@ __device__ void consume_listed(const FArgs &a, const Stage &S, int ctid, int nth
 // combinations itself, a group that spans a road boundary slot by slot.  Large roads make such
 // groups rare inside a lane's work, and keeping them in the same pass adds no extra round to
 // the chunk; small roads make them frequent, and consume_listed() is then faster.
-__device__ void consume_inline(const FArgs &a, const Stage &S, int ctid, int nthreads) {
+__device__ void consume_inline(const FArgs &a, Stage &S) {
     const int nr = S.nr;
     const int32_t cs = S.cs, ce = S.ce, g_lo = S.g_lo, g_hi = S.g_hi;
     const int64_t tile_start = S.tile_start, r_first = S.r_first;
     unsigned long long *keys = reinterpret_cast<unsigned long long *>(a.best.chi2);
-    for (int32_t g = g_lo + ctid; g < g_hi; g += nthreads) {
+    const int32_t ng = g_hi - g_lo;
+    while (true) {
+        const int32_t base = claim64(&S.work[0]);
+        if (base >= ng) break;
+        if (base + lane_id() >= ng) continue;
+        const int32_t g = g_lo + base + lane_id();
         const int32_t rel0 = g << 2;
         const int32_t first = rel0 > cs ? rel0 : cs;
         const int32_t last = (rel0 + 3 < ce - 1) ? rel0 + 3 : ce - 1;
@@ -604,15 +638,17 @@ __device__ void consume_inline(const FArgs &a, const Stage &S, int ctid, int nth
             }
         }
         if (valid_bits == 0xF) {
-            *reinterpret_cast<int4 *>(a.rec.p0 + gi) = make_int4(vp0[0], vp0[1], vp0[2], vp0[3]);
-            *reinterpret_cast<int4 *>(a.rec.p1 + gi) = make_int4(vp1[0], vp1[1], vp1[2], vp1[3]);
-            *reinterpret_cast<int4 *>(a.rec.p2 + gi) = make_int4(vp2[0], vp2[1], vp2[2], vp2[3]);
-            longlong2 *c2p = reinterpret_cast<longlong2 *>(a.rec.chi2 + gi);
-            c2p[0] = make_longlong2(vchi[0], vchi[1]);
-            c2p[1] = make_longlong2(vchi[2], vchi[3]);
-            if (a.rec.c0) *reinterpret_cast<int4 *>(a.rec.c0 + gi) = make_int4(vc0[0], vc0[1], vc0[2], vc0[3]);
-            if (a.rec.c1) *reinterpret_cast<int4 *>(a.rec.c1 + gi) = make_int4(vc1[0], vc1[1], vc1[2], vc1[3]);
-            if (a.rec.c2) *reinterpret_cast<int4 *>(a.rec.c2 + gi) = make_int4(vc2[0], vc2[1], vc2[2], vc2[3]);
+            if (a.records) {  // per-combination records (not in kept-only mode)
+                *reinterpret_cast<int4 *>(a.rec.p0 + gi) = make_int4(vp0[0], vp0[1], vp0[2], vp0[3]);
+                *reinterpret_cast<int4 *>(a.rec.p1 + gi) = make_int4(vp1[0], vp1[1], vp1[2], vp1[3]);
+                *reinterpret_cast<int4 *>(a.rec.p2 + gi) = make_int4(vp2[0], vp2[1], vp2[2], vp2[3]);
+                longlong2 *c2p = reinterpret_cast<longlong2 *>(a.rec.chi2 + gi);
+                c2p[0] = make_longlong2(vchi[0], vchi[1]);
+                c2p[1] = make_longlong2(vchi[2], vchi[3]);
+                if (a.rec.c0) *reinterpret_cast<int4 *>(a.rec.c0 + gi) = make_int4(vc0[0], vc0[1], vc0[2], vc0[3]);
+                if (a.rec.c1) *reinterpret_cast<int4 *>(a.rec.c1 + gi) = make_int4(vc1[0], vc1[1], vc1[2], vc1[3]);
+                if (a.rec.c2) *reinterpret_cast<int4 *>(a.rec.c2 + gi) = make_int4(vc2[0], vc2[1], vc2[2], vc2[3]);
+            }
             const uint32_t accw = (acc_bits & 1u) | ((acc_bits & 2u) << 7) |
                                   ((acc_bits & 4u) << 14) | ((acc_bits & 8u) << 21);
             *reinterpret_cast<uint32_t *>(a.accept + gi) = accw;
@@ -620,13 +656,15 @@ __device__ void consume_inline(const FArgs &a, const Stage &S, int ctid, int nth
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 if (valid_bits & (1u << e)) {
-                    a.rec.p0[gi + e] = vp0[e];
-                    a.rec.p1[gi + e] = vp1[e];
-                    a.rec.p2[gi + e] = vp2[e];
-                    a.rec.chi2[gi + e] = vchi[e];
-                    if (a.rec.c0) a.rec.c0[gi + e] = vc0[e];
-                    if (a.rec.c1) a.rec.c1[gi + e] = vc1[e];
-                    if (a.rec.c2) a.rec.c2[gi + e] = vc2[e];
+                    if (a.records) {
+                        a.rec.p0[gi + e] = vp0[e];
+                        a.rec.p1[gi + e] = vp1[e];
+                        a.rec.p2[gi + e] = vp2[e];
+                        a.rec.chi2[gi + e] = vchi[e];
+                        if (a.rec.c0) a.rec.c0[gi + e] = vc0[e];
+                        if (a.rec.c1) a.rec.c1[gi + e] = vc1[e];
+                        if (a.rec.c2) a.rec.c2[gi + e] = vc2[e];
+                    }
                     a.accept[gi + e] = (acc_bits >> e) & 1u;
                 }
             }
@@ -666,12 +704,12 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG == 256 ? 
     __syncthreads();
     int cur = 0;
     while (!S[cur].done) {
-        if (wave == 0)
-            produce(a, S[cur ^ 1], L, n_roads, n_combos, n_tiles, T, qlmask);
-        else if (listed)
-            consume_listed(a, S[cur], static_cast<int>(threadIdx.x) - kWaveSize, WG - kWaveSize);
+        if (wave == 0) produce(a, S[cur ^ 1], L, n_roads, n_combos, n_tiles, T, qlmask);
+        // every wave, the loader once it has staged the next chunk
+        if (listed)
+            consume_listed(a, S[cur]);
         else
-            consume_inline(a, S[cur], static_cast<int>(threadIdx.x) - kWaveSize, WG - kWaveSize);
+            consume_inline(a, S[cur]);
         __syncthreads();
         cur ^= 1;
     }
@@ -698,6 +736,7 @@ FArgs make_args(const FusedLaunch &f) {
     a.tiles_cap = f.tiles_cap;
     a.road_cap = f.road_cap;
     a.combo_cap = f.combo_cap;
+    a.records = f.kept_only ? 0 : 1;
     return a;
 }
 

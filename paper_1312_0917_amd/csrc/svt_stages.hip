@@ -416,10 +416,10 @@ __global__ __launch_bounds__(kSegThreads) void k_select_mark(svt_config cfg, svt
 
 // Parameters of combination k of road r, fitted again from the grouped coordinates and the
 // road's constant set (the same integer arithmetic as the records, so the same values).
-__device__ inline void refit_params(const svt_fconst *__restrict__ bank,
-                                    const int16_t *__restrict__ coords, int32_t shift,
-                                    uint32_t nh, int64_t hb, int32_t set, uint32_t k,
-                                    int32_t *p) {
+__device__ inline int64_t refit_combo(const svt_fconst *__restrict__ bank,
+                                     const int16_t *__restrict__ coords, int32_t shift,
+                                     uint32_t nh, int64_t hb, int32_t set, uint32_t k, int32_t *v,
+                                     int rows) {
     uint32_t h[SVT_N_LAYERS];
 #pragma unroll
     for (int l = SVT_N_LAYERS - 1; l >= 0; --l) {  // layer 0 most significant
@@ -435,14 +435,16 @@ __device__ inline void refit_params(const svt_fconst *__restrict__ bank,
         off += nh_of(nh, l);
     }
     const svt_fconst &F = bank[set];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
+    for (int j = 0; j < rows; ++j) {
         int64_t acc = F.q[j];
 #pragma unroll
         for (int l = 0; l < SVT_N_LAYERS; ++l)
             acc += static_cast<int64_t>(F.f[j][l]) * static_cast<int64_t>(x[l]);
-        p[j] = static_cast<int32_t>(acc >> shift);
+        v[j] = static_cast<int32_t>(acc >> shift);
     }
+    if (rows < 6) return 0;
+    return static_cast<int64_t>(v[3]) * v[3] + static_cast<int64_t>(v[4]) * v[4] +
+           static_cast<int64_t>(v[5]) * v[5];
 }
 
 // With bank and coords (batched path), the best track's parameters are fitted again from its
@@ -465,7 +467,11 @@ __global__ void k_best_finalize(svt_roads roads, Sizes n_roads_s, svt_fitrec rec
             uint64_t bchi = UINT64_MAX;
             int64_t bk = 0;
             for (int64_t k = 0; k < nc && cb + k < n_combos; ++k) {
-                const int64_t c2 = rec.chi2[cb + k];
+                int32_t vv[6];
+                const int64_t c2 = rec.chi2 ? rec.chi2[cb + k]
+                                            : refit_combo(bank, coords, shift, roads.nhits[r],
+                                                          roads.hit_begin[r], roads.set[r],
+                                                          static_cast<uint32_t>(k), vv, 6);
                 if (c2 <= cut && c2 >= 0 && static_cast<uint64_t>(c2) < bchi) {
                     bchi = static_cast<uint64_t>(c2);
                     bk = k;
@@ -475,9 +481,18 @@ __global__ void k_best_finalize(svt_roads roads, Sizes n_roads_s, svt_fitrec rec
                 const int64_t g = cb + bk;
                 best.k[r] = static_cast<int32_t>(bk);
                 best.chi2[r] = static_cast<int64_t>(bchi);
-                best.p0[r] = rec.p0[g];
-                best.p1[r] = rec.p1[g];
-                best.p2[r] = rec.p2[g];
+                if (rec.p0) {
+                    best.p0[r] = rec.p0[g];
+                    best.p1[r] = rec.p1[g];
+                    best.p2[r] = rec.p2[g];
+                } else {
+                    int32_t vv[6];
+                    refit_combo(bank, coords, shift, roads.nhits[r], roads.hit_begin[r],
+                                roads.set[r], static_cast<uint32_t>(bk), vv, 3);
+                    best.p0[r] = vv[0];
+                    best.p1[r] = vv[1];
+                    best.p2[r] = vv[2];
+                }
                 continue;
             }
             key = UINT64_MAX;
@@ -495,9 +510,9 @@ __global__ void k_best_finalize(svt_roads roads, Sizes n_roads_s, svt_fitrec rec
             best.chi2[r] = static_cast<int64_t>(key >> kKeyKBits);
             const bool in = g >= 0 && g < n_combos && k < nc;
             if (bank && coords && in) {
-                int32_t p[3];
-                refit_params(bank, coords, shift, roads.nhits[r], roads.hit_begin[r],
-                             roads.set[r], static_cast<uint32_t>(k), p);
+                int32_t p[6];
+                refit_combo(bank, coords, shift, roads.nhits[r], roads.hit_begin[r],
+                            roads.set[r], static_cast<uint32_t>(k), p, 3);
                 best.p0[r] = p[0];
                 best.p1[r] = p[1];
                 best.p2[r] = p[2];
@@ -508,6 +523,27 @@ __global__ void k_best_finalize(svt_roads roads, Sizes n_roads_s, svt_fitrec rec
             }
         }
     }
+}
+
+// Accept flags of combinations base .. base + 15 as a bit mask (one 16-byte load when aligned).
+__device__ inline uint32_t accept_bits16(const uint8_t *__restrict__ accept, int64_t base,
+                                         int64_t n) {
+    uint32_t bits = 0;
+    if (base + 16 <= n && (reinterpret_cast<uintptr_t>(accept + base) & 15) == 0) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(accept + base);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                bits |= ((w[q] >> (8 * c)) & 0xFFu) ? (1u << (4 * q + c)) : 0u;
+    } else {
+        for (int e = 0; e < 16; ++e) {
+            const int64_t i = base + e;
+            if (i < n && accept[i]) bits |= 1u << e;
+        }
+    }
+    return bits;
 }
 
 // ---- kept list: ascending indices of accepted combinations -------------------------------
@@ -521,11 +557,7 @@ __global__ __launch_bounds__(kSegThreads) void k_kept_write(const uint8_t *__res
     const int64_t nb = (n + kKeptBlock - 1) / kKeptBlock;
     for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
         const int64_t base = b * kKeptBlock + static_cast<int64_t>(threadIdx.x) * 16;
-        uint32_t bits = 0;
-        for (int e = 0; e < 16; ++e) {
-            const int64_t i = base + e;
-            if (i < n && accept[i]) bits |= 1u << e;
-        }
+        uint32_t bits = accept_bits16(accept, base, n);
         int64_t tot;
         int64_t pos = block_excl_scan<int64_t, kSegThreads>(__popc(bits), tmp, tot) + kb_prefix[b];
         while (bits) {
@@ -536,6 +568,97 @@ __global__ __launch_bounds__(kSegThreads) void k_kept_write(const uint8_t *__res
         }
     }
     (void)err;
+}
+
+// Kept-only mode: per block of kKeptBlock combinations, the accepted ones in ascending order.
+// One wave per block (lane i reads the flags of combinations 64 i .. 64 i + 63 of the block), so
+// that many blocks are in flight at once: the work per block is a short chain of dependent
+// reads.  The block's accepted offsets are compacted in LDS and then spread evenly over the
+// lanes.  The
+// block's roads lie between the first road of its fit tile and the first road of the next tile;
+// their combo_begin values are staged in the wave's LDS slice (up to kKeptRoads of them, else
+// searched in place), each accepted combination finds its road by binary search and is fitted
+// again from the grouped coordinates.
+constexpr int kKeptRoads = 512;
+__global__ __launch_bounds__(kSegThreads) void k_kept_refit(
+    const uint8_t *__restrict__ accept, Sizes n_s, Sizes nr_s,
+    const int64_t *__restrict__ kb_prefix, svt_roads roads,
+    const int32_t *__restrict__ tile_first_road, int64_t tile_combos,
+    const svt_fconst *__restrict__ bank, const int16_t *__restrict__ coords, int32_t shift,
+    int64_t *kept, svt_fitrec rec, int64_t kept_cap, uint64_t *err) {
+    constexpr int kWaves = kSegThreads / kWaveSize;
+    __shared__ int64_t s_cb[kWaves][kKeptRoads];
+    __shared__ uint16_t s_acc[kWaves][kKeptBlock];  // accepted offsets inside the block, in order
+    const int wv = threadIdx.x / kWaveSize;
+    const int lane = lane_id();
+    const int64_t n = load_size(n_s);
+    const int64_t n_roads = load_size(nr_s);
+    const int64_t nb = (n + kKeptBlock - 1) / kKeptBlock;
+    const int64_t n_tiles = (n + tile_combos - 1) / tile_combos;
+    for (int64_t b = static_cast<int64_t>(blockIdx.x) * kWaves + wv; b < nb;
+         b += static_cast<int64_t>(gridDim.x) * kWaves) {
+        const int64_t base = b * kKeptBlock + static_cast<int64_t>(lane) * 64;
+        uint64_t bits = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            bits |= static_cast<uint64_t>(accept_bits16(accept, base + 16 * q, n)) << (16 * q);
+        const int cnt = __popcll(bits);
+        const int incl = wave_incl_scan(cnt);
+        const int tot = __shfl(incl, kWaveSize - 1);
+        if (tot == 0) continue;  // uniform within the wave
+        const int64_t pos0 = kb_prefix[b];
+        uint16_t *acc_l = s_acc[wv];
+        {
+            int o = incl - cnt;
+            uint64_t m = bits;
+            while (m) {
+                acc_l[o++] = static_cast<uint16_t>(lane * 64 + __builtin_ctzll(m));
+                m &= m - 1;
+            }
+        }
+        const int64_t t0 = (b * kKeptBlock) / tile_combos;
+        const int64_t t1 = ((b + 1) * kKeptBlock - 1) / tile_combos + 1;
+        const int64_t r_lo = tile_first_road[t0];
+        const int64_t r_hi = t1 < n_tiles ? tile_first_road[t1] : n_roads - 1;
+        const int64_t nloc = r_hi - r_lo + 1;
+        const bool staged = nloc <= kKeptRoads;
+        int64_t *cb_l = s_cb[wv];
+        if (staged)
+            for (int64_t j = lane; j < nloc; j += kWaveSize) cb_l[j] = roads.combo_begin[r_lo + j];
+        __builtin_amdgcn_wave_barrier();  // one wave: its LDS writes precede its reads
+        // the block's accepted combinations, spread evenly over the lanes
+        for (int j = lane; j < tot; j += kWaveSize) {
+            const int64_t i = b * kKeptBlock + acc_l[j];
+            const int64_t pos = pos0 + j;
+            int64_t lo = 0, hi = nloc - 1;  // last road with combo_begin <= i
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                const int64_t cb = staged ? cb_l[mid] : roads.combo_begin[r_lo + mid];
+                if (cb <= i) lo = mid; else hi = mid - 1;
+            }
+            const int64_t r = r_lo + lo;
+            const int64_t k = i - (staged ? cb_l[lo] : roads.combo_begin[r]);
+            if (k < 0 || k >= roads.ncombo[r]) {
+                report(err, SVT_ERRCLASS_INDEX, static_cast<uint64_t>(i));
+                continue;
+            }
+            if (pos < kept_cap) {
+                int32_t v[6];
+                const int64_t c2 = refit_combo(bank, coords, shift, roads.nhits[r],
+                                               roads.hit_begin[r], roads.set[r],
+                                               static_cast<uint32_t>(k), v, 6);
+                kept[pos] = i;
+                if (rec.p0) rec.p0[pos] = v[0];
+                if (rec.p1) rec.p1[pos] = v[1];
+                if (rec.p2) rec.p2[pos] = v[2];
+                if (rec.chi2) rec.chi2[pos] = c2;
+                if (rec.c0) rec.c0[pos] = v[3];
+                if (rec.c1) rec.c1[pos] = v[4];
+                if (rec.c2) rec.c2[pos] = v[5];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();  // the slice is reused by the wave's next block
+    }
 }
 
 inline int64_t clamp_grid(int64_t blocks, int64_t maxb) {
@@ -668,4 +791,20 @@ hipError_t launch_kept_write(const uint8_t *accept, Sizes n_combos, int64_t grid
     return hipGetLastError();
 }
 
+}  // namespace svt
+
+namespace svt {
+hipError_t launch_kept_refit(const uint8_t *accept, Sizes n_combos, Sizes n_roads,
+                             int64_t grid_blocks, const int64_t *kb_prefix, const svt_roads &roads,
+                             const int32_t *tile_first_road, int64_t tile_combos,
+                             const svt_fconst *bank, const int16_t *coords, int32_t shift,
+                             int64_t *kept, const svt_fitrec &rec, int64_t kept_cap,
+                             uint64_t *err, hipStream_t s) {
+    // one wave per kept block, four per workgroup
+    const int64_t g = clamp_grid((grid_blocks + 3) / 4, 1 << 16);
+    hipLaunchKernelGGL(k_kept_refit, dim3(g), dim3(kSegThreads), 0, s, accept, n_combos, n_roads,
+                       kb_prefix, roads, tile_first_road, tile_combos, bank, coords, shift, kept,
+                       rec, kept_cap, err);
+    return hipGetLastError();
+}
 }  // namespace svt

@@ -186,7 +186,12 @@ class BatchRunner:
 
     def __init__(self, cfg: L.svt_config, bank: torch.Tensor, word_cap: int, road_cap: int,
                  combo_cap: int, kept_cap: int = 0, tune: Optional[L.svt_tune] = None,
-                 graph=True, with_c=True, device="cuda", stream=None):
+                 graph=True, with_c=True, device="cuda", stream=None, kept_only=False):
+        """``kept_only``: no per-combination records; ``rec`` then holds the fit values of the
+        accepted combinations, compacted in the order of the kept list (needs kept_cap > 0)."""
+        if kept_only and kept_cap <= 0:
+            raise ValueError("kept-only mode needs a kept list (kept_cap > 0)")
+        self.kept_only = kept_only
         self.cfg, self.bank, self.device = cfg, bank, device
         self.tune = tune if tune is not None else L.make_tune()
         self.graph = graph
@@ -199,7 +204,7 @@ class BatchRunner:
         self.d_n = torch.zeros(4, dtype=I64, device=d)  # words, roads, combos, kept
         self.d_err = torch.zeros(1, dtype=I64, device=d)
         self.roads = _alloc_roads(road_cap, d)
-        self.rec = _alloc_rec(combo_cap, d, with_c)
+        self.rec = _alloc_rec(kept_cap if kept_only else combo_cap, d, with_c)
         self.accept = torch.empty(max(combo_cap, 4) + 4, dtype=U8, device=d)
         self.best = _alloc_best(road_cap, d)
         self.kept = torch.empty(max(kept_cap, 1), dtype=I64, device=d) if kept_cap > 0 else None
@@ -239,7 +244,8 @@ class BatchRunner:
                                  self.combo_cap, self.best, self.kept, self.kept_cap,
                                  self.d_n[1:2], self.d_n[2:3],
                                  self.d_n[3:4] if self.kept_cap > 0 else None, self.d_err,
-                                 self.work, L.SVT_BATCH_GRAPH if self.graph else 0, s)
+                                 self.work, (L.SVT_BATCH_GRAPH if self.graph else 0) |
+                                 (L.SVT_BATCH_KEPT_ONLY if self.kept_only else 0), s)
         L.check(st, "svt_process_batch")
         return self
 
@@ -261,7 +267,10 @@ class BatchRunner:
         sz = self.sizes()
         nr, nc, nk = sz["n_roads"], sz["n_combos"], sz["n_kept"]
         out = {f"road_{k}": v[:nr] for k, v in self.roads.items()}
-        out.update({k: v[:nc] for k, v in self.rec.items()})
+        if self.kept_only:  # records of the kept combinations only, in kept-list order
+            out.update({f"kept_{k}": v[:nk] for k, v in self.rec.items()})
+        else:
+            out.update({k: v[:nc] for k, v in self.rec.items()})
         out["accept"] = self.accept[:nc]
         out.update({f"best_{k}": v[:nr] for k, v in self.best.items()})
         out["kept"] = self.kept[:nk] if self.kept is not None else None
