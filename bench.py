@@ -178,15 +178,19 @@ def measure_uneven(bank, steps, log_fn):
     words = P.words_tensor(sample.words)
     res = T.autotune(words, P.device_bank(bank.f, bank.q), L.make_config(chi2_cut=cut), nr, nc,
                      steps=steps, cache_path=None, use_cache=False, log=log_fn)
-    default = [row for row in res.table if row[:4] == (4096, 64, 256, 3)]
+    default = [row for row in res.table if row[:5] == (4096, 64, 256, 3, 0)]
+    flat = [row[5] for row in res.table if row[4] == 0]
+    events = [row[5] for row in res.table if row[4] == 1]
     return dict(workload=f"c3: {ne} events, {nr} roads, {len(sample.words)} hit words, "
                          f"{nc} combinations", best_tune=dict(zip(
-                             ("tile_combos", "chunk_roads", "wg_size", "wgs_per_cu"),
+                             ("tile_combos", "chunk_roads", "wg_size", "wgs_per_cu", "schedule"),
                              T.tune_tuple(res.tune))),
                 ms_per_pass_best=round(res.ms_per_pass, 5),
-                ms_per_pass_default=default[0][4] if default else None,
+                ms_per_pass_default=default[0][5] if default else None,
                 value=nc / (res.ms_per_pass * 1e-3), unit="fitted combinations/s",
-                candidates=len(res.table), all_outputs_identical=True)
+                candidates=len(res.table), all_outputs_identical=True,
+                ablation_ms_per_pass=dict(flat_tiles_best=min(flat) if flat else None,
+                                          event_per_workgroup_best=min(events) if events else None))
 
 
 def measure_serving(bank, n_events, warmup_events, rate_hz, n_slots, max_events, tune, workers):
@@ -392,6 +396,29 @@ def main():
                     kernel="k_fused", kernel_ms=round(k_ms, 5), algorithmic_bytes=alg,
                     bytes_per_combination=round(alg / n_combos, 3))
 
+    # ---- ablation: one event per workgroup instead of flat combination tiles ---------------
+    events_schedule = None
+    if not args.no_kept_only:
+        log("one event per workgroup")
+        ev_tune = L.svt_tune_resolve(L.make_tune(tune.tile_combos, tune.chunk_roads, tune.wg_size,
+                                                 4, 1))
+        er = P.BatchRunner(gcfg, dbank, n_words, n_roads, n_combos, kept_cap=0, tune=ev_tune,
+                           graph=not args.no_graph, with_c=False)
+        er.load(words)
+        for _ in range(W):
+            er.run()
+        torch.cuda.synchronize()
+        assert er.error() == (0, -1), er.error()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            er.run()
+        torch.cuda.synchronize()
+        ev_s = (time.perf_counter() - t0) / K
+        events_schedule = dict(value=n_combos / ev_s, ms_per_step=round(ev_s * 1e3, 5),
+                               flat_over_events=round(ev_s / batch_s, 2))
+        del er
+        L.svt_release_graphs()
+
     # ---- kept-only mode: no per-combination records ----------------------------------------
     kept_only = None
     if not args.no_kept_only:
@@ -463,9 +490,10 @@ def main():
                     chi2_cut=cut, path="svt_process_batch (%s)" % (
                         "direct launches" if args.no_graph else "graph replay"),
                     tune=dict(tile_combos=t.tile_combos, chunk_roads=t.chunk_roads,
-                              wg_size=t.wg_size, wgs_per_cu=t.wgs_per_cu),
+                              wg_size=t.wg_size, wgs_per_cu=t.wgs_per_cu, schedule=t.schedule),
                     device=dev_name),
-        roofline=roofline, cpu_baseline=cpu, kept_only=kept_only, plain=plain,
+        roofline=roofline, cpu_baseline=cpu, kept_only=kept_only,
+        event_per_workgroup=events_schedule, plain=plain,
         uneven_autotuned=uneven,
         serving=serving, transfer=transfer, max_scale=large)
     print(json.dumps(out), flush=True)

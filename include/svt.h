@@ -124,12 +124,16 @@ typedef struct svt_best {
     int64_t *chi2;
 } svt_best;
 
-/* Launch parameters of the persistent fused kernel; zeros pick the built-in defaults. */
+/* Launch parameters of the batched pass; zeros pick the built-in defaults. */
 typedef struct svt_tune {
     int32_t tile_combos;  /* combinations per work tile: 4096 or 8192 */
     int32_t chunk_roads;  /* roads staged in LDS at once: 64 */
     int32_t wg_size;      /* 256 or 512 (one loader wave, the rest fit) */
     int32_t wgs_per_cu;   /* persistent workgroups per compute unit, 1..8 */
+    int32_t schedule;     /* 0: persistent fused kernel over flat combination tiles (default);
+                             1: one event per workgroup at a time (the multi-core scheme of
+                             section II-A, kept as an ablation; tile_combos, chunk_roads and
+                             wg_size then only have to be valid values) */
 } svt_tune;
 
 /* ---- sizes of the caller-provided scratch ------------------------------------------------ */

@@ -44,7 +44,7 @@ class svt_best(ctypes.Structure):
 
 class svt_tune(ctypes.Structure):
     _fields_ = [("tile_combos", _I32), ("chunk_roads", _I32), ("wg_size", _I32),
-                ("wgs_per_cu", _I32)]
+                ("wgs_per_cu", _I32), ("schedule", _I32)]
 
 
 class LibraryMissing(RuntimeError):
@@ -125,8 +125,8 @@ def make_config(chi2_cut=256, shift=10, max_hits=8, n_sets=256, n_layers=5) -> s
     return svt_config(n_layers, shift, chi2_cut, max_hits, n_sets)
 
 
-def make_tune(tile_combos=0, chunk_roads=0, wg_size=0, wgs_per_cu=0) -> svt_tune:
-    return svt_tune(tile_combos, chunk_roads, wg_size, wgs_per_cu)
+def make_tune(tile_combos=0, chunk_roads=0, wg_size=0, wgs_per_cu=0, schedule=0) -> svt_tune:
+    return svt_tune(tile_combos, chunk_roads, wg_size, wgs_per_cu, schedule)
 
 
 def svt_tune_resolve(tune=None) -> svt_tune:

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsvt.so")
-SOURCES = ["svt_api.hip", "svt_stages.hip", "svt_fused.hip", "svt_prepass.hip"]
+SOURCES = ["svt_api.hip", "svt_stages.hip", "svt_fused.hip", "svt_prepass.hip", "svt_events.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

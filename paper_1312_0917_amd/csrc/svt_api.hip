@@ -51,7 +51,10 @@ UnpackWs carve_unpack(Carver &c, int64_t n_words) {
 }
 
 struct BatchWs {
-    uint32_t *tickets;  // [0] fused-kernel tiles, [1] pre-pass blocks
+    uint32_t *tickets;  // [0] fused-kernel tiles (or events), [1] pre-pass blocks
+    int64_t *n_events;  // events of the batch
+    int32_t *efr;       // first road of every event
+    int64_t events_cap;
     int64_t *status;    // look-back status words, 2 per word block
     int64_t nb;
     int32_t *tfr;
@@ -64,6 +67,9 @@ BatchWs carve_batch(Carver &c, int64_t word_cap, int64_t road_cap, int64_t combo
                     int64_t tile) {
     BatchWs w;
     w.tickets = c.take<uint32_t>(4);
+    w.n_events = c.take<int64_t>(2);
+    w.events_cap = road_cap > 0 ? road_cap : 1;  // every event holds at least one road
+    w.efr = c.take<int32_t>(w.events_cap);
     w.nb = ceil_div(word_cap > 0 ? word_cap : 1, kPrepassBlockWords);
     w.status = c.take<int64_t>(2 * w.nb);
     w.tiles_cap = ceil_div(combo_cap > 0 ? combo_cap : 1, tile) + 1;
@@ -75,12 +81,13 @@ BatchWs carve_batch(Carver &c, int64_t word_cap, int64_t road_cap, int64_t combo
 }
 
 svt_tune resolve_tune(const svt_tune *t) {
-    svt_tune r{4096, 64, 256, 3};
+    svt_tune r{4096, 64, 256, 3, 0};
     if (t) {
         if (t->tile_combos) r.tile_combos = t->tile_combos;
         if (t->chunk_roads) r.chunk_roads = t->chunk_roads;
         if (t->wg_size) r.wg_size = t->wg_size;
         if (t->wgs_per_cu) r.wgs_per_cu = t->wgs_per_cu;
+        r.schedule = t->schedule;
     }
     return r;
 }
@@ -315,12 +322,18 @@ static svt_status batch_sequence(const FusedLaunch &f, const BatchWs &w, int64_t
     p.nb_cap = w.nb;
     p.tickets = w.tickets;
     p.err = f.err;
+    p.event_first_road = w.efr;
+    p.event_cap = w.events_cap;
+    p.d_n_events = w.n_events;
     uint64_t *err = f.err;
     SVT_TRY(launch_batch_reset(p, d_n_kept, stream));
     SVT_TRY(launch_prepass(p, stream));
     if (d_n_kept) SVT_TRY(launch_zero(w.kb, w.kbn, stream));
     if (timing) SVT_TRY(hipEventRecord(g_ev_start, stream));
-    SVT_TRY(launch_fused(f, stream));
+    if (f.tune.schedule == 1)
+        SVT_TRY(launch_fit_events(f, w.efr, w.n_events, w.events_cap, stream));
+    else
+        SVT_TRY(launch_fused(f, stream));
     if (timing) SVT_TRY(hipEventRecord(g_ev_stop, stream));
     SVT_TRY(launch_best_finalize(f.roads, nr, f.kept_only ? svt_fitrec{} : f.rec, nc, f.best,
                                  f.cfg.chi2_cut, err, true, f.bank, f.coords, f.cfg.shift,
@@ -419,7 +432,8 @@ svt_status svt_process_batch(const svt_fconst *bank, const svt_config *cfg, cons
                     static_cast<uint64_t>(cfg->chi2_cut), static_cast<uint64_t>(cfg->max_hits),
                     static_cast<uint64_t>(cfg->n_sets), static_cast<uint64_t>(t.tile_combos),
                     static_cast<uint64_t>(t.chunk_roads), static_cast<uint64_t>(t.wg_size),
-                    static_cast<uint64_t>(t.wgs_per_cu), static_cast<uint64_t>(flags)};
+                    static_cast<uint64_t>(t.wgs_per_cu), static_cast<uint64_t>(t.schedule),
+                    static_cast<uint64_t>(flags)};
     std::lock_guard<std::mutex> lock(g_graph_mu);
     auto &cache = graph_cache();
     auto it = cache.find(key);

@@ -206,6 +206,10 @@ struct FusedLaunch {
     bool kept_only;            // no per-combination records (accept flags still written)
 };
 hipError_t launch_fused(const FusedLaunch &f, hipStream_t s);
+// One event per workgroup at a time (schedule 1 of svt_tune): the same outputs as the fused
+// kernel, for the ablation against flat combination tiles.
+hipError_t launch_fit_events(const FusedLaunch &f, const int32_t *event_first_road,
+                             const int64_t *d_n_events, int64_t event_cap, hipStream_t s);
 hipError_t launch_zero(int64_t *p, int64_t n, hipStream_t s);
 // Per road: turn the best-track key left in best.chi2 into (k, chi2, p0..p2), reading the
 // parameters from the records, or fitting them again from the grouped coordinates when bank
@@ -235,6 +239,9 @@ struct PrepassLaunch {
     int64_t nb_cap;            // ceil(word_cap / kPrepassBlockWords)
     uint32_t *tickets;         // [0] fused-kernel tiles, [1] pre-pass blocks
     uint64_t *err;
+    int32_t *event_first_road; // first road of every event (event_cap entries)
+    int64_t event_cap;
+    int64_t *d_n_events;
 };
 // Clears the error word, both tickets, *d_n_kept (nullable) and the status words in use.
 hipError_t launch_batch_reset(const PrepassLaunch &p, int64_t *d_n_kept, hipStream_t s);

@@ -758,7 +758,8 @@ bool fused_tune_supported(const svt_tune &t) {
     const bool tile_ok = t.tile_combos >= kKeptBlock && t.tile_combos <= kMaxTile &&
                          t.tile_combos % kKeptBlock == 0;
     const bool occ_ok = t.wgs_per_cu >= 1 && t.wgs_per_cu <= 8;
-    return wg_ok && ch_ok && tile_ok && occ_ok;
+    const bool sched_ok = t.schedule == 0 || t.schedule == 1;
+    return wg_ok && ch_ok && tile_ok && occ_ok && sched_ok;
 }
 
 hipError_t launch_fused(const FusedLaunch &f, hipStream_t s) {

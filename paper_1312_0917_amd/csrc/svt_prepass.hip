@@ -143,6 +143,9 @@ struct PArgs {
     int64_t nb_cap;
     uint32_t *ticket;
     uint64_t *err;
+    int32_t *event_first_road;
+    int64_t event_cap;
+    int64_t *d_n_events;
 };
 
 __device__ inline int64_t combos_of(uint32_t packed) {
@@ -153,7 +156,7 @@ __device__ inline int64_t combos_of(uint32_t packed) {
 }
 
 // Per owned road, in LDS: s_road[rl] = first local word (12 bits) | events started in the block
-// up to that word (12 bits) << 12; s_info[rl] = hits per layer (4 bits each) | too-many-hits
+// up to that word (12 bits) << 12 | the word starts an event << 24; s_info[rl] = hits per layer (4 bits each) | too-many-hits
 // << 20 | no-constant-set << 21.
 constexpr uint32_t kInfoOver = 1u << 20;
 constexpr uint32_t kInfoSet = 1u << 21;
@@ -180,6 +183,7 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
         if (b == 0 && tid == 0) {  // empty batch
             *a.d_n_roads = 0;
             *a.d_n_combos = 0;
+            if (a.d_n_events) *a.d_n_events = 0;
         }
         return;
     }
@@ -249,7 +253,8 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
         for (int e = 0; e < kPW; ++e) {
             ev += (emask >> e) & 1u;
             if ((rmask >> e) & 1u) s_road[rl++] = static_cast<uint32_t>(j0 + e) |
-                                                  (static_cast<uint32_t>(ev) << 12);
+                                                  (static_cast<uint32_t>(ev) << 12) |
+                                                  (((emask >> e) & 1u) << 24);
         }
         if (tid == 0) s_road[nroads] = static_cast<uint32_t>(s_tail_end);
     }
@@ -345,7 +350,10 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
             if (r >= a.road_cap) continue;
             const uint32_t rd = s_road[rl];
             const int j = rd & 0xFFF;
-            a.roads.event[r] = static_cast<int32_t>(E0 + (rd >> 12) - 1);
+            const int64_t ev = E0 + ((rd >> 12) & 0xFFF) - 1;
+            a.roads.event[r] = static_cast<int32_t>(ev);
+            if (a.event_first_road && ((rd >> 24) & 1u) && ev < a.event_cap)
+                a.event_first_road[ev] = static_cast<int32_t>(r);
             a.roads.set[r] = static_cast<int32_t>(w_rtag(sw[kOff + j]));
             a.roads.hit_begin[r] = base + j;
             a.roads.nhits[r] = info & 0xFFFFFu;
@@ -370,6 +378,7 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
         const int64_t n_combos = s_pre[2] + tc;
         *a.d_n_roads = n_roads;
         *a.d_n_combos = n_combos;
+        if (a.d_n_events) *a.d_n_events = E0 + te;
         if (n_roads > a.road_cap) report(a.err, SVT_ERRCLASS_CAPACITY, 0);
         if (n_combos > a.combo_cap) report(a.err, SVT_ERRCLASS_CAPACITY, 1);
     }
@@ -415,6 +424,9 @@ hipError_t launch_prepass(const PrepassLaunch &p, hipStream_t s) {
     a.nb_cap = p.nb_cap;
     a.ticket = p.tickets + 1;
     a.err = p.err;
+    a.event_first_road = p.event_first_road;
+    a.event_cap = p.event_cap;
+    a.d_n_events = p.d_n_events;
     const int64_t grid = p.nb_cap > 0 ? p.nb_cap : 1;
     hipLaunchKernelGGL(k_prepass, dim3(static_cast<unsigned>(grid)), dim3(kPT), 0, s, a);
     return hipGetLastError();

@@ -27,13 +27,18 @@ CHUNK_ROADS = 64
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "svt_tune.json")
 
 
+EVENT_OCCUPANCIES = (2, 4)
+
+
 def candidates():
-    return [L.make_tune(t, CHUNK_ROADS, wg, occ)
+    """Flat-tile shapes of the fused kernel, plus the one-event-per-workgroup schedule."""
+    flat = [L.make_tune(t, CHUNK_ROADS, wg, occ)
             for t in TILES for wg in WG_SIZES for occ in OCCUPANCIES]
+    return flat + [L.make_tune(4096, CHUNK_ROADS, 256, occ, 1) for occ in EVENT_OCCUPANCIES]
 
 
 def tune_tuple(t: L.svt_tune):
-    return (t.tile_combos, t.chunk_roads, t.wg_size, t.wgs_per_cu)
+    return (t.tile_combos, t.chunk_roads, t.wg_size, t.wgs_per_cu, t.schedule)
 
 
 def workload_key(n_words: int, n_roads: int, n_combos: int, device: str) -> str:
@@ -48,7 +53,7 @@ def workload_key(n_words: int, n_roads: int, n_combos: int, device: str) -> str:
 class TuneResult:
     tune: L.svt_tune
     ms_per_pass: float
-    table: list  # (tile, chunk, wg, occ, ms)
+    table: list  # (tile, chunk, wg, occ, schedule, ms)
 
 
 def _digest(res: dict) -> str:

@@ -39,7 +39,7 @@ def test_abi_version_and_struct_sizes():
     lib = L.load()
     assert lib.svt_abi_version() == 1
     assert ctypes.sizeof(L.svt_config) == 24
-    assert ctypes.sizeof(L.svt_tune) == 16
+    assert ctypes.sizeof(L.svt_tune) == 20
     rec = L.pack_bank(__import__("numpy").zeros((2, 6, 5), "int16"),
                       __import__("numpy").zeros((2, 6), "int32"))
     assert rec.shape == (2, 88)
@@ -115,10 +115,10 @@ def test_product_path_does_not_import_the_oracle():
 
 def test_tune_resolution_fills_defaults_and_rejects_unbuilt_shapes():
     t = L.svt_tune_resolve()
-    assert (t.tile_combos, t.chunk_roads, t.wg_size, t.wgs_per_cu) == (4096, 64, 256, 3)
-    t = L.svt_tune_resolve(L.make_tune(8192, 0, 512, 0))
-    assert (t.tile_combos, t.chunk_roads, t.wg_size, t.wgs_per_cu) == (8192, 64, 512, 3)
+    assert (t.tile_combos, t.chunk_roads, t.wg_size, t.wgs_per_cu, t.schedule) == (4096, 64, 256, 3, 0)
+    t = L.svt_tune_resolve(L.make_tune(8192, 0, 512, 0, 1))
+    assert (t.tile_combos, t.chunk_roads, t.wg_size, t.wgs_per_cu, t.schedule) == (8192, 64, 512, 3, 1)
     for bad in [L.make_tune(wg_size=128), L.make_tune(tile_combos=6000),
-                L.make_tune(chunk_roads=32), L.make_tune(wgs_per_cu=9)]:
+                L.make_tune(chunk_roads=32), L.make_tune(wgs_per_cu=9), L.make_tune(schedule=2)]:
         with pytest.raises(L.SvtError):
             L.svt_tune_resolve(bad)

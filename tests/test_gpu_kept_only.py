@@ -70,6 +70,14 @@ def test_kept_only_tiny_streams_and_extreme_constants(seed):
     check(ref, runner.result(), f"tiny seed {seed}")
 
 
+def test_kept_only_with_event_per_workgroup_schedule(bank):
+    s = synth.make_sample("c3", bank=bank)
+    ref = oracle.run(s.words, bank.f, bank.q, CFG)
+    runner = run_kept_only(s.words, bank.f, bank.q, CFG, ref, graph=False,
+                           tune=L.make_tune(4096, 64, 256, 4, 1))
+    check(ref, runner.result(), "kept-only, events per workgroup")
+
+
 def test_kept_only_capacity_reports_required_size(bank):
     s = synth.make_sample("c1", bank=bank)
     ref = oracle.run(s.words, bank.f, bank.q, CFG)

@@ -18,7 +18,8 @@ pytestmark = pytest.mark.gpu
 
 CFG = oracle.make_config(chi2_cut=synth.DEFAULT_CHI2_CUT)
 TUNES = [L.make_tune(4096, 64, 256, 2), L.make_tune(8192, 64, 256, 3),
-         L.make_tune(4096, 64, 512, 1), L.make_tune(8192, 64, 512, 2)]
+         L.make_tune(4096, 64, 512, 1), L.make_tune(8192, 64, 512, 2),
+         L.make_tune(4096, 64, 256, 4, 1)]  # the last: one event per workgroup
 
 
 @pytest.fixture(scope="module")
@@ -46,6 +47,17 @@ def test_batch_path_matches_oracle(samples, bank, config, graph):
     if graph:  # a replay of the captured graph gives the same bytes
         runner.run()
         compare(ref, runner.result(), BATCH_KEYS, f"batch {config} replay")
+    L.svt_release_graphs()
+
+
+@pytest.mark.parametrize("config", ["c1", "c2", "c3"])
+def test_event_per_workgroup_schedule_matches_oracle(samples, bank, config):
+    """Schedule 1 (one event per workgroup) against the oracle, with and without graphs."""
+    s, ref = samples[config]
+    for graph in (False, True):
+        got, runner = run_batch(s.words, bank.f, bank.q, CFG, ref=ref, graph=graph,
+                                tune=L.make_tune(4096, 64, 256, 4, 1))
+        compare(ref, got, BATCH_KEYS, f"events {config} graph={graph}")
     L.svt_release_graphs()
 
 
