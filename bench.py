@@ -150,7 +150,9 @@ def measure_large(config, n_events, passes, tune, bank, workers=16):
     out = dict(workload=f"{config}: {n_events} events, {n_roads} roads, {n_words} hit words, "
                         f"{n_combos} combinations",
                value=n_combos / dt, unit="fitted combinations/s", ms_per_pass=round(dt * 1e3, 4),
-               passes=passes,
+               passes=passes, tune=dict(tile_combos=tune.tile_combos, chunk_roads=tune.chunk_roads,
+                                        wg_size=tune.wg_size, wgs_per_cu=tune.wgs_per_cu,
+                                        schedule=tune.schedule),
                roofline=dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                              frac=round(ach / HBM_PEAK_GBS, 4),
                              traffic=recorded_traffic(config, n_events), kernel="k_fused",
@@ -319,6 +321,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=100e3)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--no-kept-only", action="store_true", help="skip the kept-only mode run")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the default launch shape instead of the autotuned one")
     ap.add_argument("--transfer-reps", type=int, default=10,
                     help="packets per point of the transfer study; 0 skips it")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -362,7 +366,19 @@ def main():
     gcfg = L.make_config(chi2_cut=cut)
     dbank = P.device_bank(bank.f, bank.q)
     words = P.words_tensor(sample.words)
+    explicit_tune = any((args.tile, args.chunk, args.wg, args.occ))
     tune = L.svt_tune_resolve(L.make_tune(args.tile, args.chunk, args.wg, args.occ))
+    default_tune = L.svt_tune_resolve(None)
+    tuned = None
+    if not explicit_tune and not args.no_autotune:
+        # the autotuner picks the launch shape of this batch (every candidate must write the
+        # same bytes); the timed steps below then use the winner
+        from paper_1312_0917_amd import tune as T
+        log("autotuning the batch")
+        res = T.autotune(words, dbank, gcfg, n_roads, n_combos, steps=10, cache_path=None,
+                         use_cache=False)
+        tune = res.tune
+        tuned = dict(candidates=len(res.table), best_ms_per_pass=round(res.ms_per_pass, 5))
 
     # ---- batched path: resident buffers, graph replay -------------------------------------
     runner = P.BatchRunner(gcfg, dbank, n_words, n_roads, n_combos, kept_cap=0, tune=tune,
@@ -470,8 +486,8 @@ def main():
         L.svt_release_graphs()
         del runner
         torch.cuda.empty_cache()
-        large = measure_large("c5", args.large_events, args.large_passes, tune, bank,
-                              args.workers)
+        large = measure_large("c5", args.large_events, args.large_passes,
+                              tune if explicit_tune else default_tune, bank, args.workers)
 
     cpu = None
     if not args.no_cpu:
@@ -491,6 +507,7 @@ def main():
                         "direct launches" if args.no_graph else "graph replay"),
                     tune=dict(tile_combos=t.tile_combos, chunk_roads=t.chunk_roads,
                               wg_size=t.wg_size, wgs_per_cu=t.wgs_per_cu, schedule=t.schedule),
+                    autotune=tuned,
                     device=dev_name),
         roofline=roofline, cpu_baseline=cpu, kept_only=kept_only,
         event_per_workgroup=events_schedule, plain=plain,

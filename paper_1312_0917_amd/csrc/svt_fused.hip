@@ -53,6 +53,7 @@ struct FArgs {
     int64_t road_cap;
     int64_t combo_cap;
     int32_t records;        // 0: kept-only mode, no per-combination records
+    int32_t fold;           // shift <= 15: ql packed with f_j4 (see fit_xyz)
 };
 
 // Per-road indexing data of the current chunk, in LDS (32 bytes).
@@ -85,6 +86,14 @@ __device__ __forceinline__ int32_t dot2(int32_t a, int32_t b, int32_t c) {
                                   false);
 }
 
+// a.lo * b.lo + a.hi * b.hi, the VOP3P form with an inline zero accumulator: the compiler
+// otherwise picks the accumulate-in-place encoding and copies a zero into every accumulator.
+__device__ __forceinline__ int32_t dot2_zero(int32_t a, int32_t b) {
+    int32_t r;
+    asm("v_dot2_i32_i16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 // floor(k / n) for 0 <= k < 2^15 and 1 <= n <= 64 with m = ceil(2^23 / n) < 2^24, using the
 // full-rate 24-bit multiply: (k * 2^9) * m / 2^32 = k * m / 2^23 and k * (m * n - 2^23) <
 // 2^15 * 64 < 2^23, so the high word is exactly floor(k / n) (n = 1 included).
@@ -114,26 +123,27 @@ struct Fit {
     int64_t chi2;
 };
 
-// Fit combination k of a road.  k = (i01 * n23 + i23) * n4 + h4, where i01 = h0 * n1 + h1
-// and i23 = h2 * n3 + h3 index the coordinate-pair tables.  Each sum
+// The six rows of one combination from its three coordinate pairs.  Each sum
 //     ql_j + f_j0 x0 + f_j1 x1 + f_j2 x2 + f_j3 x3 + f_j4 x4
 // is three packed 16-bit dot products; |sum| < 2^30 + 5 * 2^27 < 2^31, so int32 is exact.
-__device__ __forceinline__ Fit fit_combo(const RoadMeta &m, const RoadConst &c, uint32_t k,
-                                         const int32_t *XT, int32_t shift) {
-    const uint32_t n4 = m.nn & 0xFFu, n23 = m.nn >> 8;
-    const uint32_t q4 = div_small(k, m.m4);
-    const uint32_t h4 = k - mul_u24(q4, n4);
-    const uint32_t i01 = div_small(q4, m.m23);
-    const uint32_t i23 = q4 - mul_u24(i01, n23);
-    const int32_t x01 = XT[m.b01 + static_cast<int32_t>(i01)];
-    const int32_t x23 = XT[m.b23 + static_cast<int32_t>(i23)];
-    const int32_t x4 = XT[m.b4 + static_cast<int32_t>(h4)];
+// With FOLD (shift <= 15, so 0 <= ql < 2^15) ql rides in the layer-4 pair, (f_j4, ql_j) .
+// (x4, 1), and every row starts from zero instead of from a copy of ql.
+template <bool FOLD>
+__device__ __forceinline__ Fit fit_xyz(const RoadConst &c, int32_t x01, int32_t x23, int32_t x4,
+                                       int32_t shift) {
     Fit f;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-        int32_t acc = dot2(c.F01[j], x01, c.ql[j]);
-        acc = dot2(c.F23[j], x23, acc);
-        acc = dot2(c.F4[j], x4, acc);
+        int32_t acc;
+        if (FOLD) {
+            acc = dot2_zero(c.F4[j], x4);
+            acc = dot2(c.F01[j], x01, acc);
+            acc = dot2(c.F23[j], x23, acc);
+        } else {
+            acc = dot2(c.F01[j], x01, c.ql[j]);
+            acc = dot2(c.F23[j], x23, acc);
+            acc = dot2(c.F4[j], x4, acc);
+        }
         f.v[j] = (acc >> shift) + c.qh[j];
     }
     f.chi2 = static_cast<int64_t>(f.v[3]) * f.v[3] + static_cast<int64_t>(f.v[4]) * f.v[4] +
@@ -141,6 +151,50 @@ __device__ __forceinline__ Fit fit_combo(const RoadMeta &m, const RoadConst &c, 
     return f;
 }
 
+// Fit combination k of a road.  k = (i01 * n23 + i23) * n4 + h4, where i01 = h0 * n1 + h1
+// and i23 = h2 * n3 + h3 index the coordinate-pair tables.
+template <bool FOLD>
+__device__ __forceinline__ Fit fit_combo(const RoadMeta &m, const RoadConst &c, uint32_t k,
+                                         const int32_t *XT, int32_t shift) {
+    const uint32_t n4 = m.nn & 0xFFu, n23 = m.nn >> 8;
+    const uint32_t q4 = div_small(k, m.m4);
+    const uint32_t h4 = k - mul_u24(q4, n4);
+    const uint32_t i01 = div_small(q4, m.m23);
+    const uint32_t i23 = q4 - mul_u24(i01, n23);
+    return fit_xyz<FOLD>(c, XT[m.b01 + static_cast<int32_t>(i01)],
+                         XT[m.b23 + static_cast<int32_t>(i23)],
+                         XT[m.b4 + static_cast<int32_t>(h4)], shift);
+}
+
+// Four consecutive combinations k0, k0 + 1, k0 + 2, k0 + 3 of one road (k0 may lie up to 3
+// outside [0, C); those slots get a harmless dummy).  The table indices of the first are
+// divided out once and the others stepped from it, carrying h4 -> i23 -> i01.
+template <bool FOLD>
+__device__ __forceinline__ void fit4(const RoadMeta &m, const RoadConst &c, int32_t k0,
+                                     const int32_t *XT, int32_t shift, Fit *out) {
+    const int32_t C = m.C;
+    const uint32_t n4 = m.nn & 0xFFu, n23 = m.nn >> 8;
+    const uint32_t k = static_cast<uint32_t>(k0 < 0 ? 0 : (k0 > C - 1 ? C - 1 : k0));
+    const uint32_t q4 = div_small(k, m.m4);
+    uint32_t h4 = k - mul_u24(q4, n4);
+    uint32_t i01 = div_small(q4, m.m23);
+    uint32_t i23 = q4 - mul_u24(i01, n23);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        out[e] = fit_xyz<FOLD>(c, XT[m.b01 + static_cast<int32_t>(i01)],
+                               XT[m.b23 + static_cast<int32_t>(i23)],
+                               XT[m.b4 + static_cast<int32_t>(h4)], shift);
+        if (e < 3 && k0 + e >= 0 && k0 + e + 1 < C) {  // step to k0 + e + 1
+            ++h4;
+            const bool w4 = h4 == n4;
+            h4 = w4 ? 0u : h4;
+            i23 += w4 ? 1u : 0u;
+            const bool w23 = i23 == n23;
+            i23 = w23 ? 0u : i23;
+            i01 += w23 ? 1u : 0u;
+        }
+    }
+}
 
 // One staged chunk: up to 64 consecutive roads of a tile.
 struct Stage {
@@ -298,7 +352,8 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
             for (int j = 0; j < 6; ++j) {
                 rc.F01[j] = pack16(f_el(fw, 5 * j + 0), f_el(fw, 5 * j + 1));
                 rc.F23[j] = pack16(f_el(fw, 5 * j + 2), f_el(fw, 5 * j + 3));
-                rc.F4[j] = pack16(f_el(fw, 5 * j + 4), 0);
+                rc.F4[j] = pack16(f_el(fw, 5 * j + 4),
+                                  a.fold ? static_cast<int32_t>(static_cast<uint32_t>(qv[j]) & qlmask) : 0);
                 rc.qh[j] = qv[j] >> a.shift;
                 rc.ql[j] = static_cast<int32_t>(static_cast<uint32_t>(qv[j]) & qlmask);
             }
@@ -324,7 +379,7 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
                     for (int32_t h3 = 0; h3 < n3; ++h3)
                         S.XT[b23 + h2 * n3 + h3] = pack16(x2, S.G[off3 + h3]);
                 }
-                for (int32_t h4 = 0; h4 < n4; ++h4) S.XT[b4 + h4] = pack16(S.G[off4 + h4], 0);
+                for (int32_t h4 = 0; h4 < n4; ++h4) S.XT[b4 + h4] = pack16(S.G[off4 + h4], 1);
             }
             // groups whose first combination inside [cs, ce) belongs to this road
             const int32_t glo = rb <= cs ? g_lo : (rb + 3) >> 2;
@@ -413,6 +468,7 @@ __device__ __forceinline__ void store_group(const FArgs &a, int64_t gi, uint32_t
 
 // A group whose valid slots all lie in staged road ri: four fits with one road's constants
 // (slots outside `slots` compute a harmless dummy, k = 0, and are not written).
+template <bool FOLD>
 __device__ __forceinline__ void fit_group(const FArgs &a, const Stage &S, int ri, int32_t rel0,
                                           uint32_t slots, int64_t tile_start, int64_t r_first) {
     const RoadMeta m = S.meta[ri];
@@ -421,14 +477,15 @@ __device__ __forceinline__ void fit_group(const FArgs &a, const Stage &S, int ri
     int32_t vp0[4], vp1[4], vp2[4], vc0[4], vc1[4], vc2[4];
     int64_t vchi[4];
     int32_t kk[4];
+    Fit f4r[4];
+    fit4<FOLD>(m, c, rel0 - rbase, S.XT, a.shift, f4r);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const int32_t k = ((slots >> e) & 1u) ? rel0 + e - rbase : 0;
-        const Fit f = fit_combo(m, c, static_cast<uint32_t>(k), S.XT, a.shift);
+        const Fit &f = f4r[e];
         vp0[e] = f.v[0]; vp1[e] = f.v[1]; vp2[e] = f.v[2];
         vc0[e] = f.v[3]; vc1[e] = f.v[4]; vc2[e] = f.v[5];
         vchi[e] = f.chi2;
-        kk[e] = k;
+        kk[e] = rel0 + e - rbase;
     }
     uint32_t acc_bits = 0;
 #pragma unroll
@@ -456,6 +513,7 @@ __device__ __forceinline__ void fit_group(const FArgs &a, const Stage &S, int ri
 // A group that spans road boundaries: each slot is fitted with the constants of its own road
 // (road ri holds the first valid slot; later roads follow in staging order) and written on its
 // own.  Rare (at most one group per road), so it is kept small rather than fast.
+template <bool FOLD>
 __device__ void fit_group_split(const FArgs &a, const Stage &S, int ri, int32_t rel0,
                                 uint32_t slots, int64_t tile_start, int64_t r_first) {
     const int nr = S.nr;
@@ -468,7 +526,7 @@ __device__ void fit_group_split(const FArgs &a, const Stage &S, int ri, int32_t 
         const int32_t ci = rel0 + e;
         while (r + 1 < nr && ci >= S.rb[r] + S.meta[r].C) ++r;  // skips empty roads
         const int32_t k = ci - S.rb[r];
-        const Fit f = fit_combo(S.meta[r], S.rc[r], static_cast<uint32_t>(k), S.XT, a.shift);
+        const Fit f = fit_combo<FOLD>(S.meta[r], S.rc[r], static_cast<uint32_t>(k), S.XT, a.shift);
         const bool acc = f.chi2 <= a.cut;
         if (a.records) {
             a.rec.p0[gi + e] = f.v[0];
@@ -494,6 +552,7 @@ __device__ void fit_group_split(const FArgs &a, const Stage &S, int ri, int32_t 
 // road take the uniform path (one road's constants, full 16-byte stores); the few groups that
 // span a road boundary are listed by the loader and fitted after the others, each slot with its
 // own road, so that every group is written by exactly one lane.
+template <bool FOLD>
 __device__ void consume_listed(const FArgs &a, Stage &S) {
     const int32_t cs = S.cs, ce = S.ce, g_lo = S.g_lo, g_hi = S.g_hi;
     const int64_t tile_start = S.tile_start, r_first = S.r_first;
@@ -515,7 +574,7 @@ __device__ void consume_listed(const FArgs &a, Stage &S) {
                 in_ri |= (rel0 + e < end) ? (1u << e) : 0u;
             }
             // a group spanning a road boundary is a listed group, fitted below
-            if (!(valid & ~in_ri)) fit_group(a, S, ri, rel0, valid, tile_start, r_first);
+            if (!(valid & ~in_ri)) fit_group<FOLD>(a, S, ri, rel0, valid, tile_start, r_first);
         }
     }
     const int32_t nx = S.nx;
@@ -530,7 +589,7 @@ __device__ void consume_listed(const FArgs &a, Stage &S) {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
                 valid |= (rel0 + e >= cs && rel0 + e < ce) ? (1u << e) : 0u;
-            fit_group_split(a, S, S.M[off], rel0, valid, tile_start, r_first);
+            fit_group_split<FOLD>(a, S, S.M[off], rel0, valid, tile_start, r_first);
         }
     }
 }
@@ -539,6 +598,7 @@ __device__ void consume_listed(const FArgs &a, Stage &S) {
 // combinations itself, a group that spans a road boundary slot by slot.  Large roads make such
 // groups rare inside a lane's work, and keeping them in the same pass adds no extra round to
 // the chunk; small roads make them frequent, and consume_listed() is then faster.
+template <bool FOLD>
 __device__ void consume_inline(const FArgs &a, Stage &S) {
     const int nr = S.nr;
     const int32_t cs = S.cs, ce = S.ce, g_lo = S.g_lo, g_hi = S.g_hi;
@@ -569,14 +629,15 @@ __device__ void consume_inline(const FArgs &a, Stage &S) {
             // every valid combination of the group is in road ri: four independent fits
             // (invalid slots compute a dummy k = 0)
             const RoadConst c = S.rc[ri];
+            Fit f4r[4];
+            fit4<FOLD>(m, c, rel0 - rbase, S.XT, a.shift, f4r);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int32_t k = (valid_bits >> e) & 1u ? rel0 + e - rbase : 0;
-                const Fit f = fit_combo(m, c, static_cast<uint32_t>(k), S.XT, a.shift);
+                const Fit &f = f4r[e];
                 vp0[e] = f.v[0]; vp1[e] = f.v[1]; vp2[e] = f.v[2];
                 vc0[e] = f.v[3]; vc1[e] = f.v[4]; vc2[e] = f.v[5];
                 vchi[e] = f.chi2;
-                kk[e] = k;
+                kk[e] = rel0 + e - rbase;
                 rr4[e] = ri;
             }
         } else {
@@ -597,7 +658,7 @@ __device__ void consume_inline(const FArgs &a, Stage &S) {
                         }
                         c = S.rc[ri];
                     }
-                    const Fit f = fit_combo(m, c, static_cast<uint32_t>(k), S.XT, a.shift);
+                    const Fit f = fit_combo<FOLD>(m, c, static_cast<uint32_t>(k), S.XT, a.shift);
                     vp0[e] = f.v[0]; vp1[e] = f.v[1]; vp2[e] = f.v[2];
                     vc0[e] = f.v[3]; vc1[e] = f.v[4]; vc2[e] = f.v[5];
                     vchi[e] = f.chi2;
@@ -672,7 +733,7 @@ __device__ void consume_inline(const FArgs &a, Stage &S) {
     }
 }
 
-template <int WG>
+template <int WG, bool FOLD>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG == 256 ? 3 : 2))) void k_fused(FArgs a) {
     static_assert(WG > kWaveSize, "one loader wave plus compute waves");
     __shared__ Stage S[2];
@@ -707,9 +768,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG == 256 ? 
         if (wave == 0) produce(a, S[cur ^ 1], L, n_roads, n_combos, n_tiles, T, qlmask);
         // every wave, the loader once it has staged the next chunk
         if (listed)
-            consume_listed(a, S[cur]);
+            consume_listed<FOLD>(a, S[cur]);
         else
-            consume_inline(a, S[cur]);
+            consume_inline<FOLD>(a, S[cur]);
         __syncthreads();
         cur ^= 1;
     }
@@ -737,12 +798,16 @@ FArgs make_args(const FusedLaunch &f) {
     a.road_cap = f.road_cap;
     a.combo_cap = f.combo_cap;
     a.records = f.kept_only ? 0 : 1;
+    a.fold = f.cfg.shift <= 15 ? 1 : 0;
     return a;
 }
 
 template <int WG>
 hipError_t launch_fused_t(const FArgs &a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_fused<WG>), dim3(grid), dim3(WG), 0, s, a);
+    if (a.fold)
+        hipLaunchKernelGGL((k_fused<WG, true>), dim3(grid), dim3(WG), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_fused<WG, false>), dim3(grid), dim3(WG), 0, s, a);
     return hipGetLastError();
 }
 
