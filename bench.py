@@ -473,13 +473,16 @@ def main():
     serving = None
     if args.serve_events > 0:
         log(f"serving: {args.serve_events} events at {args.serve_rate:.0f} Hz")
+        # small batches: the default launch shape (the autotuner's pick is for the big batch)
         serving = measure_serving(bank, args.serve_events, args.serve_warmup, args.serve_rate,
-                                  args.serve_slots, 256, tune, args.workers)
+                                  args.serve_slots, 256, tune if explicit_tune else default_tune,
+                                  args.workers)
 
     transfer = None
     if args.transfer_reps > 0:
         log("transfer study")
-        transfer = measure_transfer(bank, tune, args.transfer_reps, args.workers)
+        transfer = measure_transfer(bank, tune if explicit_tune else default_tune,
+                                    args.transfer_reps, args.workers)
 
     large = None
     if args.large_events > 0:

@@ -223,6 +223,18 @@ void svt_set_fused_timing_events(hipEvent_t start, hipEvent_t stop);
  * Host call, no allocation. */
 svt_status svt_mapped_pointer(void *host, void **dev);
 
+/* Host plumbing for callers that drive batches from a host loop (the serving form), so that a
+ * binding needs no runtime handle of its own: an asynchronous copy on `stream` between
+ * page-locked host memory and device memory (kind SVT_COPY_H2D or SVT_COPY_D2H; bytes >= 0;
+ * the host side must stay untouched until the copy has run), an event recorded on a stream,
+ * and a poll of such an event (1 done, 0 pending, SVT_ERR_HIP on a runtime error). */
+#define SVT_COPY_H2D 1
+#define SVT_COPY_D2H 2
+svt_status svt_copy_async(void *dst, const void *src, int64_t bytes, int32_t kind,
+                          hipStream_t stream);
+svt_status svt_event_record(hipEvent_t event, hipStream_t stream);
+int32_t svt_event_done(hipEvent_t event);
+
 /* Destroy every cached graph (call before freeing buffers a cached graph refers to). */
 void svt_release_graphs(void);
 

@@ -19,6 +19,8 @@ SVT_ERR_CAPACITY, SVT_ERR_HIP, SVT_ERR_SET = -4, -5, -6
 SVT_NO_ERROR = (1 << 64) - 1
 SVT_BATCH_GRAPH = 1
 SVT_BATCH_KEPT_ONLY = 2
+SVT_COPY_H2D = 1
+SVT_COPY_D2H = 2
 
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -86,6 +88,9 @@ def load():
         "svt_release_graphs": (None, []),
         "svt_tune_resolve": (_I32, [S(svt_tune), S(svt_tune)]),
         "svt_mapped_pointer": (_I32, [_P, S(_P)]),
+        "svt_copy_async": (_I32, [_P, _P, _I64, _I32, _P]),
+        "svt_event_record": (_I32, [_P, _P]),
+        "svt_event_done": (_I32, [_P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -100,7 +105,7 @@ def exported_symbols():
             "svt_combine_workspace", "svt_select_workspace", "svt_batch_workspace", "svt_unpack",
             "svt_combine", "svt_fit", "svt_select", "svt_process_batch",
             "svt_set_fused_timing_events", "svt_release_graphs", "svt_tune_resolve",
-            "svt_mapped_pointer"]
+            "svt_mapped_pointer", "svt_copy_async", "svt_event_record", "svt_event_done"]
 
 
 # ---- marshalling helpers -----------------------------------------------------------------
@@ -245,6 +250,26 @@ def svt_process_batch(bank, cfg, tune, words, d_n_words, word_cap, roads, road_c
                                     work.numel() * work.element_size(), flags, _stream(stream))
 
 
+class PreparedBatch:
+    """The argument list of svt_process_batch built once for a fixed set of buffers, so that a
+    host loop pays one foreign call per batch (words, flags and stream may change per call)."""
+
+    def __init__(self, bank, cfg, tune, d_n_words, word_cap, roads, road_cap, rec, accept,
+                 combo_cap, best, kept, kept_cap, d_n_roads, d_n_combos, d_n_kept, d_err, work):
+        self._keep = (roads_struct(roads), fitrec_struct(rec), best_struct(best), cfg,
+                      tune if tune is not None else make_tune())
+        r, rc, b, c, t = self._keep
+        self._head = (_ptr(bank), ctypes.byref(c), ctypes.byref(t))
+        self._tail = (_ptr(d_n_words), word_cap, ctypes.byref(r), road_cap, ctypes.byref(rc),
+                      _ptr(accept), combo_cap, ctypes.byref(b), _ptr(kept), kept_cap,
+                      _ptr(d_n_roads), _ptr(d_n_combos), _ptr(d_n_kept), _ptr(d_err), _ptr(work),
+                      work.numel() * work.element_size())
+        self._fn = load().svt_process_batch
+
+    def __call__(self, words, flags, stream) -> int:
+        return self._fn(*self._head, _ptr(words), *self._tail, flags, _stream(stream))
+
+
 def svt_set_fused_timing_events(start, stop):
     load().svt_set_fused_timing_events(start.cuda_event if start is not None else None,
                                        stop.cuda_event if stop is not None else None)
@@ -252,6 +277,23 @@ def svt_set_fused_timing_events(start, stop):
 
 def svt_release_graphs():
     load().svt_release_graphs()
+
+
+def svt_copy_async(dst, src, nbytes, kind, stream):
+    check(load().svt_copy_async(_ptr(dst), _ptr(src), int(nbytes), kind, _stream(stream)),
+          "svt_copy_async")
+
+
+def svt_event_record(event, stream):
+    """``event``: a torch.cuda.Event that has been recorded once (so that it exists)."""
+    check(load().svt_event_record(event.cuda_event, _stream(stream)), "svt_event_record")
+
+
+def svt_event_done(event) -> bool:
+    r = load().svt_event_done(event.cuda_event)
+    if r < 0:
+        raise SvtError(r, "svt_event_done")
+    return r == 1
 
 
 def svt_mapped_pointer(host) -> int:

@@ -130,6 +130,30 @@ extern "C" {
 
 int32_t svt_abi_version(void) { return SVT_ABI_VERSION; }
 
+svt_status svt_copy_async(void *dst, const void *src, int64_t bytes, int32_t kind,
+                          hipStream_t stream) {
+    if (bytes < 0 || (bytes > 0 && (!dst || !src))) return SVT_ERR_ARG;
+    if (kind != SVT_COPY_H2D && kind != SVT_COPY_D2H) return SVT_ERR_ARG;
+    if (bytes == 0) return SVT_OK;
+    const hipMemcpyKind k = kind == SVT_COPY_H2D ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
+    return hipMemcpyAsync(dst, src, static_cast<size_t>(bytes), k, stream) == hipSuccess
+               ? SVT_OK
+               : SVT_ERR_HIP;
+}
+
+svt_status svt_event_record(hipEvent_t event, hipStream_t stream) {
+    if (!event) return SVT_ERR_ARG;
+    return hipEventRecord(event, stream) == hipSuccess ? SVT_OK : SVT_ERR_HIP;
+}
+
+int32_t svt_event_done(hipEvent_t event) {
+    if (!event) return SVT_ERR_ARG;
+    const hipError_t e = hipEventQuery(event);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) return 0;
+    return SVT_ERR_HIP;
+}
+
 svt_status svt_mapped_pointer(void *host, void **dev) {
     if (!host || !dev) return SVT_ERR_ARG;
     *dev = nullptr;

@@ -201,8 +201,10 @@ class BatchRunner:
         self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
         d = device
         self.words = torch.zeros(max(word_cap, 1), dtype=I32, device=d)
-        self.d_n = torch.zeros(4, dtype=I64, device=d)  # words, roads, combos, kept
-        self.d_err = torch.zeros(1, dtype=I64, device=d)
+        # words, roads, combos, kept, then the error word: one copy brings all five back
+        self.d_state = torch.zeros(5, dtype=I64, device=d)
+        self.d_n = self.d_state[0:4]
+        self.d_err = self.d_state[4:5]
         self.roads = _alloc_roads(road_cap, d)
         self.rec = _alloc_rec(kept_cap if kept_only else combo_cap, d, with_c)
         self.accept = torch.empty(max(combo_cap, 4) + 4, dtype=U8, device=d)
@@ -212,6 +214,12 @@ class BatchRunner:
         if nbytes < 0:
             raise ValueError("unsupported tune / capacities")
         self.work = _ws(nbytes, d)
+        self._call = L.PreparedBatch(self.bank, self.cfg, self.tune, self.d_n[0:1], self.word_cap,
+                                     self.roads, self.road_cap, self.rec, self.accept,
+                                     self.combo_cap, self.best, self.kept, self.kept_cap,
+                                     self.d_n[1:2], self.d_n[2:3],
+                                     self.d_n[3:4] if self.kept_cap > 0 else None, self.d_err,
+                                     self.work)
 
     def load(self, words: torch.Tensor, n_words: Optional[int] = None):
         """Copy a batch of words into the resident buffer and set the device word count."""
@@ -239,13 +247,8 @@ class BatchRunner:
         resident one."""
         s = stream if stream is not None else self.stream
         src = self.words if words is None else words
-        st = L.svt_process_batch(self.bank, self.cfg, self.tune, src, self.d_n[0:1],
-                                 self.word_cap, self.roads, self.road_cap, self.rec, self.accept,
-                                 self.combo_cap, self.best, self.kept, self.kept_cap,
-                                 self.d_n[1:2], self.d_n[2:3],
-                                 self.d_n[3:4] if self.kept_cap > 0 else None, self.d_err,
-                                 self.work, (L.SVT_BATCH_GRAPH if self.graph else 0) |
-                                 (L.SVT_BATCH_KEPT_ONLY if self.kept_only else 0), s)
+        st = self._call(src, (L.SVT_BATCH_GRAPH if self.graph else 0) |
+                        (L.SVT_BATCH_KEPT_ONLY if self.kept_only else 0), s)
         L.check(st, "svt_process_batch")
         return self
 

@@ -142,8 +142,10 @@ class GpuSlot:
     """Fused persistent pass on its own stream: pinned words -> H2D -> graph replay -> D2H.
 
     Results come back in two steps so that only what the batch produced crosses PCIe: the
-    sizes and error word first, then (once they are on the host) exactly n_roads entries of
-    the per-road best tracks, their event ordinals and constant sets.
+    sizes and error word first (one 40-byte copy), then, once they are on the host, exactly
+    n_roads entries of the per-road best tracks, their event ordinals and constant sets.  Every
+    step is a single foreign call (prepared batch arguments, library copy and event helpers),
+    so that the host loop's cost per batch stays small next to the arrival gaps.
     """
 
     BEST_KEYS = ("n_accept", "k", "p0", "p1", "p2", "chi2")
@@ -152,9 +154,10 @@ class GpuSlot:
                  graph: bool = True, keep_results: bool = False):
         import torch
 
+        from . import _lib as L
         from . import pipeline as P
 
-        self.torch = torch
+        self.torch, self.L = torch, L
         self.runner = P.BatchRunner(cfg, bank, word_cap, road_cap, combo_cap, kept_cap=0,
                                     tune=tune, graph=graph, with_c=False)
         self.stream = self.runner.stream
@@ -162,14 +165,24 @@ class GpuSlot:
         self.keep = keep_results
         self.h_words = torch.empty(word_cap, dtype=torch.int32, pin_memory=True)
         self.h_words_np = self.h_words.numpy().view(np.uint32)
-        self.h_sizes = torch.empty(4, dtype=torch.int64, pin_memory=True)
-        self.h_err = torch.empty(1, dtype=torch.int64, pin_memory=True)
+        self.h_n = torch.empty(1, dtype=torch.int64, pin_memory=True)
+        self.h_n_np = self.h_n.numpy()
+        self.h_state = torch.empty(5, dtype=torch.int64, pin_memory=True)  # sizes[4], error
+        self.h_state_np = self.h_state.numpy()
         self.h_best = {k: torch.empty(road_cap, dtype=v.dtype, pin_memory=True)
                        for k, v in self.runner.best.items()}
         self.h_event = torch.empty(road_cap, dtype=torch.int32, pin_memory=True)
         self.h_set = torch.empty(road_cap, dtype=torch.int32, pin_memory=True)
+        # (device array, host array, element size) of the per-road results
+        self._fetch = [(self.runner.best[k], self.h_best[k], self.h_best[k].element_size())
+                       for k in self.BEST_KEYS]
+        self._fetch += [(self.runner.roads["event"], self.h_event, 4),
+                        (self.runner.roads["set"], self.h_set, 4)]
         self.sizes_ev = torch.cuda.Event()
         self.done_ev = torch.cuda.Event()
+        for ev in (self.sizes_ev, self.done_ev):  # create the events
+            ev.record(self.stream)
+        torch.cuda.synchronize()
         self.retries = 0
         self.batch = None
         self.stage = 0  # 1: sizes in flight, 2: results in flight, 3: complete
@@ -180,45 +193,38 @@ class GpuSlot:
         return n_words <= self.word_cap
 
     def _enqueue(self, words: np.ndarray):
-        torch = self.torch
+        L, r, s = self.L, self.runner, self.stream
         n = len(words)
         self.h_words_np[:n] = words
-        r = self.runner
-        with torch.cuda.stream(self.stream):
-            r.words[:n].copy_(self.h_words[:n], non_blocking=True)
-            r.d_n[0].fill_(n)
+        self.h_n_np[0] = n
+        L.svt_copy_async(r.d_n, self.h_n, 8, L.SVT_COPY_H2D, s)
+        L.svt_copy_async(r.words, self.h_words, 4 * n, L.SVT_COPY_H2D, s)
         r.run()
-        with torch.cuda.stream(self.stream):
-            self.h_sizes.copy_(r.d_n, non_blocking=True)
-            self.h_err.copy_(r.d_err, non_blocking=True)
-        self.sizes_ev.record(self.stream)
+        L.svt_copy_async(self.h_state, r.d_state, 40, L.SVT_COPY_D2H, s)
+        L.svt_event_record(self.sizes_ev, s)
         self.stage = 1
 
     def _error(self):
-        from . import _lib as L
-
-        err = int(self.h_err[0]) & L.SVT_NO_ERROR
+        L = self.L
+        err = int(self.h_state_np[4]) & L.SVT_NO_ERROR
         return L.error_decode(err) if err != L.SVT_NO_ERROR else (0, -1)
 
     def poll(self) -> bool:
+        L = self.L
         if self.stage == 1:
-            if not self.sizes_ev.query():
+            if not L.svt_event_done(self.sizes_ev):
                 return False
-            nr = int(self.h_sizes[1])
+            nr = int(self.h_state_np[1])
             if self._error()[0] != 0 or not 0 <= nr <= self.road_cap:
                 self.stage = 3
                 return True
-            torch, r = self.torch, self.runner
-            with torch.cuda.stream(self.stream):
-                for k in self.BEST_KEYS:
-                    self.h_best[k][:nr].copy_(r.best[k][:nr], non_blocking=True)
-                self.h_event[:nr].copy_(r.roads["event"][:nr], non_blocking=True)
-                self.h_set[:nr].copy_(r.roads["set"][:nr], non_blocking=True)
-            self.done_ev.record(self.stream)
+            for d, h, size in self._fetch:
+                L.svt_copy_async(h, d, size * nr, L.SVT_COPY_D2H, self.stream)
+            L.svt_event_record(self.done_ev, self.stream)
             self.stage = 2
             return False
         if self.stage == 2:
-            if not self.done_ev.query():
+            if not L.svt_event_done(self.done_ev):
                 return False
             self.stage = 3
         return self.stage == 3
@@ -233,11 +239,10 @@ class GpuSlot:
         self._enqueue(words)
 
     def collect(self):
-        from . import _lib as L
-
+        L = self.L
         words, e0, e1 = self.batch
         st, idx = self._error()
-        sizes = self.h_sizes.tolist()
+        sizes = [int(v) for v in self.h_state_np[:4]]
         if st == L.SVT_ERR_CAPACITY and e1 - e0 > 1:
             # more roads or combinations than this slot holds: split at an event boundary
             # and run the halves synchronously (rare when slots are sized for the stream)
