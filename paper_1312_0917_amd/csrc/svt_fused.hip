@@ -113,6 +113,19 @@ __host__ __device__ constexpr uint32_t magic_of(uint32_t n) {
     return static_cast<uint32_t>(((1u << 23) + n - 1) / n);
 }
 
+// 16-byte stores marked non-temporal: the per-combination records are written once and read
+// by nothing later in the pass, so they should not displace the staged inputs in the caches.
+typedef int32_t nt_i32x4 __attribute__((ext_vector_type(4)));
+typedef int64_t nt_i64x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void store_nt(int32_t *p, const int32_t *v) {
+    const nt_i32x4 x = {v[0], v[1], v[2], v[3]};
+    __builtin_nontemporal_store(x, reinterpret_cast<nt_i32x4 *>(p));
+}
+__device__ __forceinline__ void store_nt(int64_t *p, int64_t a, int64_t b) {
+    const nt_i64x2 x = {a, b};
+    __builtin_nontemporal_store(x, reinterpret_cast<nt_i64x2 *>(p));
+}
+
 __device__ __forceinline__ int32_t pack16(int32_t lo, int32_t hi) {
     return static_cast<int32_t>((static_cast<uint32_t>(lo) & 0xFFFFu) |
                                 (static_cast<uint32_t>(hi) << 16));
@@ -434,15 +447,14 @@ __device__ __forceinline__ void store_group(const FArgs &a, int64_t gi, uint32_t
                                             const int32_t *vc2, const int64_t *vchi) {
     if (slots == 0xF) {
         if (a.records) {  // per-combination records (not in kept-only mode)
-            *reinterpret_cast<int4 *>(a.rec.p0 + gi) = make_int4(vp0[0], vp0[1], vp0[2], vp0[3]);
-            *reinterpret_cast<int4 *>(a.rec.p1 + gi) = make_int4(vp1[0], vp1[1], vp1[2], vp1[3]);
-            *reinterpret_cast<int4 *>(a.rec.p2 + gi) = make_int4(vp2[0], vp2[1], vp2[2], vp2[3]);
-            longlong2 *c2p = reinterpret_cast<longlong2 *>(a.rec.chi2 + gi);
-            c2p[0] = make_longlong2(vchi[0], vchi[1]);
-            c2p[1] = make_longlong2(vchi[2], vchi[3]);
-            if (a.rec.c0) *reinterpret_cast<int4 *>(a.rec.c0 + gi) = make_int4(vc0[0], vc0[1], vc0[2], vc0[3]);
-            if (a.rec.c1) *reinterpret_cast<int4 *>(a.rec.c1 + gi) = make_int4(vc1[0], vc1[1], vc1[2], vc1[3]);
-            if (a.rec.c2) *reinterpret_cast<int4 *>(a.rec.c2 + gi) = make_int4(vc2[0], vc2[1], vc2[2], vc2[3]);
+            store_nt(a.rec.p0 + gi, vp0);
+            store_nt(a.rec.p1 + gi, vp1);
+            store_nt(a.rec.p2 + gi, vp2);
+            store_nt(a.rec.chi2 + gi, vchi[0], vchi[1]);
+            store_nt(a.rec.chi2 + gi + 2, vchi[2], vchi[3]);
+            if (a.rec.c0) store_nt(a.rec.c0 + gi, vc0);
+            if (a.rec.c1) store_nt(a.rec.c1 + gi, vc1);
+            if (a.rec.c2) store_nt(a.rec.c2 + gi, vc2);
         }
         const uint32_t accw = (acc_bits & 1u) | ((acc_bits & 2u) << 7) |
                               ((acc_bits & 4u) << 14) | ((acc_bits & 8u) << 21);
@@ -701,38 +713,7 @@ __device__ void consume_inline(const FArgs &a, Stage &S) {
                     }
             }
         }
-        if (valid_bits == 0xF) {
-            if (a.records) {  // per-combination records (not in kept-only mode)
-                *reinterpret_cast<int4 *>(a.rec.p0 + gi) = make_int4(vp0[0], vp0[1], vp0[2], vp0[3]);
-                *reinterpret_cast<int4 *>(a.rec.p1 + gi) = make_int4(vp1[0], vp1[1], vp1[2], vp1[3]);
-                *reinterpret_cast<int4 *>(a.rec.p2 + gi) = make_int4(vp2[0], vp2[1], vp2[2], vp2[3]);
-                longlong2 *c2p = reinterpret_cast<longlong2 *>(a.rec.chi2 + gi);
-                c2p[0] = make_longlong2(vchi[0], vchi[1]);
-                c2p[1] = make_longlong2(vchi[2], vchi[3]);
-                if (a.rec.c0) *reinterpret_cast<int4 *>(a.rec.c0 + gi) = make_int4(vc0[0], vc0[1], vc0[2], vc0[3]);
-                if (a.rec.c1) *reinterpret_cast<int4 *>(a.rec.c1 + gi) = make_int4(vc1[0], vc1[1], vc1[2], vc1[3]);
-                if (a.rec.c2) *reinterpret_cast<int4 *>(a.rec.c2 + gi) = make_int4(vc2[0], vc2[1], vc2[2], vc2[3]);
-            }
-            const uint32_t accw = (acc_bits & 1u) | ((acc_bits & 2u) << 7) |
-                                  ((acc_bits & 4u) << 14) | ((acc_bits & 8u) << 21);
-            *reinterpret_cast<uint32_t *>(a.accept + gi) = accw;
-        } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                if (valid_bits & (1u << e)) {
-                    if (a.records) {
-                        a.rec.p0[gi + e] = vp0[e];
-                        a.rec.p1[gi + e] = vp1[e];
-                        a.rec.p2[gi + e] = vp2[e];
-                        a.rec.chi2[gi + e] = vchi[e];
-                        if (a.rec.c0) a.rec.c0[gi + e] = vc0[e];
-                        if (a.rec.c1) a.rec.c1[gi + e] = vc1[e];
-                        if (a.rec.c2) a.rec.c2[gi + e] = vc2[e];
-                    }
-                    a.accept[gi + e] = (acc_bits >> e) & 1u;
-                }
-            }
-        }
+        store_group(a, gi, valid_bits, acc_bits, vp0, vp1, vp2, vc0, vc1, vc2, vchi);
     }
 }
 
