@@ -29,6 +29,9 @@ constexpr int kChunk = 64;             // roads staged per chunk: one loader lan
 constexpr int kWordCap = 2048;         // coordinates staged per chunk (a road has at most 40)
 constexpr int kTabCap = 2048;          // coordinate-pair table entries per chunk (<= 136/road)
 constexpr int kMapCap = kMaxTile / 4;  // groups of 4 combinations in a tile
+constexpr int kRecNone = 0;  // no per-combination records (kept-only output)
+constexpr int kRecFit = 1;   // p0..p2 and chi2
+constexpr int kRecRows = 2;  // also the constraint rows c0..c2 (each pointer may be null)
 constexpr int64_t kListedMaxMean = 48;  // mean combinations per road below which road-spanning
                                         // groups get a pass of their own (consume_listed)
 
@@ -56,27 +59,37 @@ struct FArgs {
     int32_t fold;           // shift <= 15: ql packed with f_j4 (see fit_xyz)
 };
 
-// Per-road indexing data of the current chunk, in LDS (32 bytes).
+// Per-road indexing data of the current chunk, in LDS, packed into 16 bytes so that the reads
+// of the roads one wave works on fall in different banks.  Field widths: n4 <= 8 and
+// n2 * n3 <= 64 fit the top byte above a 24-bit division magic; table indices are below
+// kTabCap and C <= 8^5, so each fits 16 bits.
 struct alignas(16) RoadMeta {
-    int32_t C;      // combinations
-    uint32_t m4;    // division magic of n4
-    uint32_t m23;   // division magic of n2 * n3
-    uint32_t nn;    // n4 | (n2 * n3) << 8
-    int32_t b01;    // table index of the (h0, h1) coordinate pairs
-    int32_t b23;    // table index of the (h2, h3) pairs
-    int32_t b4;     // table index of the layer-4 coordinates
-    int32_t wo;     // first staged word of the road
+    uint32_t w4;     // division magic of n4 (low 24 bits) | n4 << 24
+    uint32_t w23;    // division magic of n2 * n3 (low 24 bits) | (n2 * n3) << 24
+    uint32_t b0123;  // table index of the (h0, h1) coordinate pairs | that of the (h2, h3)
+                     // pairs << 16
+    uint32_t b4c;    // table index of the layer-4 coordinates | combinations << 16
+    __device__ int32_t C() const { return static_cast<int32_t>(b4c >> 16); }
+    __device__ uint32_t n4() const { return w4 >> 24; }
+    __device__ uint32_t n23() const { return w23 >> 24; }
+    __device__ int32_t b01() const { return static_cast<int32_t>(b0123 & 0xFFFFu); }
+    __device__ int32_t b23() const { return static_cast<int32_t>(b0123 >> 16); }
+    __device__ int32_t b4() const { return static_cast<int32_t>(b4c & 0xFFFFu); }
 };
+static_assert(sizeof(RoadMeta) == 16, "LDS bank spread of the per-road indexing data");
 
-// Per-road constants of the current chunk, packed for the dot products (128 bytes).
+// Per-road constants of the current chunk, packed for the dot products.  144 bytes: with a
+// stride of 36 dwords the 16-byte reads of the (up to 8) roads one wave works on start in
+// different LDS banks; a 128-byte stride puts them all in the same few banks.
 struct alignas(16) RoadConst {
     int32_t F01[6];  // (f[j][0], f[j][1]) as an int16 pair
     int32_t F23[6];  // (f[j][2], f[j][3])
     int32_t F4[6];   // (f[j][4], 0)
     int32_t ql[6];   // q[j] mod 2^shift
     int32_t qh[6];   // floor(q[j] / 2^shift)
-    int32_t pad[2];
+    int32_t pad[6];
 };
+static_assert(sizeof(RoadConst) == 144, "LDS bank spread of the per-road constants");
 
 typedef short v2s __attribute__((ext_vector_type(2)));
 
@@ -169,14 +182,14 @@ __device__ __forceinline__ Fit fit_xyz(const RoadConst &c, int32_t x01, int32_t 
 template <bool FOLD>
 __device__ __forceinline__ Fit fit_combo(const RoadMeta &m, const RoadConst &c, uint32_t k,
                                          const int32_t *XT, int32_t shift) {
-    const uint32_t n4 = m.nn & 0xFFu, n23 = m.nn >> 8;
-    const uint32_t q4 = div_small(k, m.m4);
+    const uint32_t n4 = m.n4(), n23 = m.n23();
+    const uint32_t q4 = div_small(k, m.w4);
     const uint32_t h4 = k - mul_u24(q4, n4);
-    const uint32_t i01 = div_small(q4, m.m23);
+    const uint32_t i01 = div_small(q4, m.w23);
     const uint32_t i23 = q4 - mul_u24(i01, n23);
-    return fit_xyz<FOLD>(c, XT[m.b01 + static_cast<int32_t>(i01)],
-                         XT[m.b23 + static_cast<int32_t>(i23)],
-                         XT[m.b4 + static_cast<int32_t>(h4)], shift);
+    return fit_xyz<FOLD>(c, XT[m.b01() + static_cast<int32_t>(i01)],
+                         XT[m.b23() + static_cast<int32_t>(i23)],
+                         XT[m.b4() + static_cast<int32_t>(h4)], shift);
 }
 
 // Four consecutive combinations k0, k0 + 1, k0 + 2, k0 + 3 of one road (k0 may lie up to 3
@@ -185,18 +198,18 @@ __device__ __forceinline__ Fit fit_combo(const RoadMeta &m, const RoadConst &c, 
 template <bool FOLD>
 __device__ __forceinline__ void fit4(const RoadMeta &m, const RoadConst &c, int32_t k0,
                                      const int32_t *XT, int32_t shift, Fit *out) {
-    const int32_t C = m.C;
-    const uint32_t n4 = m.nn & 0xFFu, n23 = m.nn >> 8;
+    const int32_t C = m.C();
+    const uint32_t n4 = m.n4(), n23 = m.n23();
     const uint32_t k = static_cast<uint32_t>(k0 < 0 ? 0 : (k0 > C - 1 ? C - 1 : k0));
-    const uint32_t q4 = div_small(k, m.m4);
+    const uint32_t q4 = div_small(k, m.w4);
     uint32_t h4 = k - mul_u24(q4, n4);
-    uint32_t i01 = div_small(q4, m.m23);
+    uint32_t i01 = div_small(q4, m.w23);
     uint32_t i23 = q4 - mul_u24(i01, n23);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        out[e] = fit_xyz<FOLD>(c, XT[m.b01 + static_cast<int32_t>(i01)],
-                               XT[m.b23 + static_cast<int32_t>(i23)],
-                               XT[m.b4 + static_cast<int32_t>(h4)], shift);
+        out[e] = fit_xyz<FOLD>(c, XT[m.b01() + static_cast<int32_t>(i01)],
+                               XT[m.b23() + static_cast<int32_t>(i23)],
+                               XT[m.b4() + static_cast<int32_t>(h4)], shift);
         if (e < 3 && k0 + e >= 0 && k0 + e + 1 < C) {  // step to k0 + e + 1
             ++h4;
             const bool w4 = h4 == n4;
@@ -347,14 +360,11 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
         }
         if (fits) {
             RoadMeta m;
-            m.C = C;
-            m.m4 = magic_of(n4);
-            m.m23 = magic_of(n2 * n3);
-            m.nn = static_cast<uint32_t>(n4) | (static_cast<uint32_t>(n2 * n3) << 8);
-            m.b01 = to;
-            m.b23 = to + n0 * n1;
-            m.b4 = to + n0 * n1 + n2 * n3;
-            m.wo = wo;
+            const uint32_t n23 = static_cast<uint32_t>(n2 * n3);
+            m.w4 = magic_of(n4 > 0 ? n4 : 1) | (static_cast<uint32_t>(n4) << 24);
+            m.w23 = magic_of(n23 > 0 ? n23 : 1) | (n23 << 24);
+            m.b0123 = static_cast<uint32_t>(to) | (static_cast<uint32_t>(to + n0 * n1) << 16);
+            m.b4c = static_cast<uint32_t>(to + n0 * n1 + n2 * n3) | (static_cast<uint32_t>(C) << 16);
             S.meta[lane] = m;
             S.rb[lane] = rb;
             const int32_t qv[6] = {static_cast<int32_t>(qw[0].x), static_cast<int32_t>(qw[0].y),
@@ -370,7 +380,8 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
                 rc.qh[j] = qv[j] >> a.shift;
                 rc.ql[j] = static_cast<int32_t>(static_cast<uint32_t>(qv[j]) & qlmask);
             }
-            rc.pad[0] = rc.pad[1] = 0;
+#pragma unroll
+            for (int j = 0; j < 6; ++j) rc.pad[j] = 0;
             S.rc[lane] = rc;
         }
         __builtin_amdgcn_wave_barrier();  // one wave: its LDS writes precede its later reads
@@ -440,18 +451,21 @@ __device__ __forceinline__ int32_t claim64(int32_t *counter) {
 
 // Write the records of one group of 4 consecutive combinations (global index gi of slot 0):
 // one 16-byte store per array when all four slots are written, else one store per slot.
+template <int REC>
 __device__ __forceinline__ void store_group(const FArgs &a, int64_t gi, uint32_t slots,
                                             uint32_t acc_bits, const int32_t *vp0,
                                             const int32_t *vp1, const int32_t *vp2,
                                             const int32_t *vc0, const int32_t *vc1,
                                             const int32_t *vc2, const int64_t *vchi) {
     if (slots == 0xF) {
-        if (a.records) {  // per-combination records (not in kept-only mode)
+        if (REC != kRecNone) {  // per-combination records (not in kept-only mode)
             store_nt(a.rec.p0 + gi, vp0);
             store_nt(a.rec.p1 + gi, vp1);
             store_nt(a.rec.p2 + gi, vp2);
             store_nt(a.rec.chi2 + gi, vchi[0], vchi[1]);
             store_nt(a.rec.chi2 + gi + 2, vchi[2], vchi[3]);
+        }
+        if (REC == kRecRows) {
             if (a.rec.c0) store_nt(a.rec.c0 + gi, vc0);
             if (a.rec.c1) store_nt(a.rec.c1 + gi, vc1);
             if (a.rec.c2) store_nt(a.rec.c2 + gi, vc2);
@@ -463,11 +477,13 @@ __device__ __forceinline__ void store_group(const FArgs &a, int64_t gi, uint32_t
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             if (slots & (1u << e)) {
-                if (a.records) {
+                if (REC != kRecNone) {
                     a.rec.p0[gi + e] = vp0[e];
                     a.rec.p1[gi + e] = vp1[e];
                     a.rec.p2[gi + e] = vp2[e];
                     a.rec.chi2[gi + e] = vchi[e];
+                }
+                if (REC == kRecRows) {
                     if (a.rec.c0) a.rec.c0[gi + e] = vc0[e];
                     if (a.rec.c1) a.rec.c1[gi + e] = vc1[e];
                     if (a.rec.c2) a.rec.c2[gi + e] = vc2[e];
@@ -480,7 +496,7 @@ __device__ __forceinline__ void store_group(const FArgs &a, int64_t gi, uint32_t
 
 // A group whose valid slots all lie in staged road ri: four fits with one road's constants
 // (slots outside `slots` compute a harmless dummy, k = 0, and are not written).
-template <bool FOLD>
+template <bool FOLD, int REC>
 __device__ __forceinline__ void fit_group(const FArgs &a, const Stage &S, int ri, int32_t rel0,
                                           uint32_t slots, int64_t tile_start, int64_t r_first) {
     const RoadMeta m = S.meta[ri];
@@ -519,13 +535,13 @@ __device__ __forceinline__ void fit_group(const FArgs &a, const Stage &S, int ri
         atomicMin(keys + r_first + ri, kmin);
         atomicAdd(a.best.n_accept + r_first + ri, __popc(acc_bits));
     }
-    store_group(a, gi, slots, acc_bits, vp0, vp1, vp2, vc0, vc1, vc2, vchi);
+    store_group<REC>(a, gi, slots, acc_bits, vp0, vp1, vp2, vc0, vc1, vc2, vchi);
 }
 
 // A group that spans road boundaries: each slot is fitted with the constants of its own road
 // (road ri holds the first valid slot; later roads follow in staging order) and written on its
 // own.  Rare (at most one group per road), so it is kept small rather than fast.
-template <bool FOLD>
+template <bool FOLD, int REC>
 __device__ void fit_group_split(const FArgs &a, const Stage &S, int ri, int32_t rel0,
                                 uint32_t slots, int64_t tile_start, int64_t r_first) {
     const int nr = S.nr;
@@ -536,15 +552,17 @@ __device__ void fit_group_split(const FArgs &a, const Stage &S, int ri, int32_t 
     for (int e = 0; e < 4; ++e) {
         if (!((slots >> e) & 1u)) continue;
         const int32_t ci = rel0 + e;
-        while (r + 1 < nr && ci >= S.rb[r] + S.meta[r].C) ++r;  // skips empty roads
+        while (r + 1 < nr && ci >= S.rb[r] + S.meta[r].C()) ++r;  // skips empty roads
         const int32_t k = ci - S.rb[r];
         const Fit f = fit_combo<FOLD>(S.meta[r], S.rc[r], static_cast<uint32_t>(k), S.XT, a.shift);
         const bool acc = f.chi2 <= a.cut;
-        if (a.records) {
+        if (REC != kRecNone) {
             a.rec.p0[gi + e] = f.v[0];
             a.rec.p1[gi + e] = f.v[1];
             a.rec.p2[gi + e] = f.v[2];
             a.rec.chi2[gi + e] = f.chi2;
+        }
+        if (REC == kRecRows) {
             if (a.rec.c0) a.rec.c0[gi + e] = f.v[3];
             if (a.rec.c1) a.rec.c1[gi + e] = f.v[4];
             if (a.rec.c2) a.rec.c2[gi + e] = f.v[5];
@@ -567,7 +585,7 @@ __device__ void fit_group_split(const FArgs &a, const Stage &S, int ri, int32_t 
 // main pass complete their cache lines while the lines are still in L2 (the other order
 // leaves 16-byte holes that are filled too late and reach HBM twice: 1.37x the algorithmic
 // writes at c2 against 1.18x).
-template <bool FOLD>
+template <bool FOLD, int REC>
 __device__ void consume_listed(const FArgs &a, Stage &S) {
     const int32_t cs = S.cs, ce = S.ce, g_lo = S.g_lo, g_hi = S.g_hi;
     const int64_t tile_start = S.tile_start, r_first = S.r_first;
@@ -585,7 +603,7 @@ __device__ void consume_listed(const FArgs &a, Stage &S) {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
                 valid |= (rel0 + e >= cs && rel0 + e < ce) ? (1u << e) : 0u;
-            fit_group_split<FOLD>(a, S, S.M[off], rel0, valid, tile_start, r_first);
+            fit_group_split<FOLD, REC>(a, S, S.M[off], rel0, valid, tile_start, r_first);
         }
     }
     while (true) {
@@ -596,7 +614,7 @@ __device__ void consume_listed(const FArgs &a, Stage &S) {
             const int32_t g = g_lo + it;
             const int32_t rel0 = g << 2;
             const int ri = S.M[it];
-            const int32_t end = S.rb[ri] + S.meta[ri].C;  // end of road ri
+            const int32_t end = S.rb[ri] + S.meta[ri].C();  // end of road ri
             uint32_t valid = 0, in_ri = 0;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -604,7 +622,7 @@ __device__ void consume_listed(const FArgs &a, Stage &S) {
                 in_ri |= (rel0 + e < end) ? (1u << e) : 0u;
             }
             // a group spanning a road boundary is a listed group, fitted below
-            if (!(valid & ~in_ri)) fit_group<FOLD>(a, S, ri, rel0, valid, tile_start, r_first);
+            if (!(valid & ~in_ri)) fit_group<FOLD, REC>(a, S, ri, rel0, valid, tile_start, r_first);
         }
     }
 }
@@ -613,7 +631,7 @@ __device__ void consume_listed(const FArgs &a, Stage &S) {
 // combinations itself, a group that spans a road boundary slot by slot.  Large roads make such
 // groups rare inside a lane's work, and keeping them in the same pass adds no extra round to
 // the chunk; small roads make them frequent, and consume_listed() is then faster.
-template <bool FOLD>
+template <bool FOLD, int REC>
 __device__ void consume_inline(const FArgs &a, Stage &S) {
     const int nr = S.nr;
     const int32_t cs = S.cs, ce = S.ce, g_lo = S.g_lo, g_hi = S.g_hi;
@@ -639,7 +657,7 @@ __device__ void consume_inline(const FArgs &a, Stage &S) {
         int64_t vchi[4];
         int32_t kk[4];
         int rr4[4];
-        const bool one_road = last - rbase < m.C;
+        const bool one_road = last - rbase < m.C();
         if (one_road) {
             // every valid combination of the group is in road ri: four independent fits
             // (invalid slots compute a dummy k = 0)
@@ -665,9 +683,9 @@ __device__ void consume_inline(const FArgs &a, Stage &S) {
                 kk[e] = 0;
                 rr4[e] = ri;
                 if ((valid_bits >> e) & 1u) {
-                    if (k >= m.C) {
-                        while (k >= m.C && ri + 1 < nr) {  // bounded by the chunk
-                            k -= m.C;
+                    if (k >= m.C()) {
+                        while (k >= m.C() && ri + 1 < nr) {  // bounded by the chunk
+                            k -= m.C();
                             ++ri;
                             m = S.meta[ri];
                         }
@@ -713,11 +731,11 @@ __device__ void consume_inline(const FArgs &a, Stage &S) {
                     }
             }
         }
-        store_group(a, gi, valid_bits, acc_bits, vp0, vp1, vp2, vc0, vc1, vc2, vchi);
+        store_group<REC>(a, gi, valid_bits, acc_bits, vp0, vp1, vp2, vc0, vc1, vc2, vchi);
     }
 }
 
-template <int WG, bool FOLD>
+template <int WG, bool FOLD, int REC>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG == 256 ? 3 : 2))) void k_fused(FArgs a) {
     static_assert(WG > kWaveSize, "one loader wave plus compute waves");
     __shared__ Stage S[2];
@@ -752,9 +770,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG == 256 ? 
         if (wave == 0) produce(a, S[cur ^ 1], L, n_roads, n_combos, n_tiles, T, qlmask);
         // every wave, the loader once it has staged the next chunk
         if (listed)
-            consume_listed<FOLD>(a, S[cur]);
+            consume_listed<FOLD, REC>(a, S[cur]);
         else
-            consume_inline<FOLD>(a, S[cur]);
+            consume_inline<FOLD, REC>(a, S[cur]);
         __syncthreads();
         cur ^= 1;
     }
@@ -786,12 +804,22 @@ FArgs make_args(const FusedLaunch &f) {
     return a;
 }
 
+template <int WG, int REC>
+void launch_fused_r(const FArgs &a, int grid, hipStream_t s) {
+    if (a.fold)
+        hipLaunchKernelGGL((k_fused<WG, true, REC>), dim3(grid), dim3(WG), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_fused<WG, false, REC>), dim3(grid), dim3(WG), 0, s, a);
+}
+
 template <int WG>
 hipError_t launch_fused_t(const FArgs &a, int grid, hipStream_t s) {
-    if (a.fold)
-        hipLaunchKernelGGL((k_fused<WG, true>), dim3(grid), dim3(WG), 0, s, a);
+    if (a.records == 0)
+        launch_fused_r<WG, kRecNone>(a, grid, s);
+    else if (a.rec.c0 || a.rec.c1 || a.rec.c2)
+        launch_fused_r<WG, kRecRows>(a, grid, s);
     else
-        hipLaunchKernelGGL((k_fused<WG, false>), dim3(grid), dim3(WG), 0, s, a);
+        launch_fused_r<WG, kRecFit>(a, grid, s);
     return hipGetLastError();
 }
 
