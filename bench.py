@@ -214,25 +214,30 @@ def measure_serving(bank, n_events, warmup_events, rate_hz, n_slots, max_events,
     combo_cap = int(max_events * mean_c * 1.6)
     cfg = L.make_config(chi2_cut=synth.config_chi2_cut("c4"))
     dbank = P.device_bank(bank.f, bank.q)
-    slots = [serve.GpuSlot(cfg, dbank, word_cap, word_cap // 5 + 1, combo_cap, tune=tune)
-             for _ in range(n_slots)]
-    # capture each slot's graph before the clock starts
     warm = serve.EventStream(sample.words, sample.event_word_begin, np.zeros(n_events))
-    for sl in slots:
-        sl.launch(warm.slice(0, 1), 0, 1)
-        sl._wait()
-        sl.collect()
-    stats, _ = serve.serve(st, slots, max_events=max_events)
-    batched = stats.summary(warmup_events)
+    out = {}
+    for io in ("mapped", "copy"):
+        slots = [serve.GpuSlot(cfg, dbank, word_cap, word_cap // 5 + 1, combo_cap, tune=tune,
+                               io=io) for _ in range(n_slots)]
+        # capture each slot's graph before the clock starts
+        for sl in slots:
+            sl.launch(warm.slice(0, 1), 0, 1)
+            sl._wait()
+            sl.collect()
+        stats, _ = serve.serve(st, slots, max_events=max_events)
+        out[io] = stats.summary(warmup_events)
+        L.svt_release_graphs()
+        del slots
+        torch.cuda.empty_cache()
     pstats, _ = serve.serve(st, [serve.PlainSlot(cfg, dbank)], max_events=max_events)
     plain = pstats.summary(warmup_events)
-    L.svt_release_graphs()
-    del slots
-    torch.cuda.empty_cache()
     return dict(workload=f"c4: {n_events} events ({warmup_events} warm-up) arriving as a "
                          f"Poisson stream at {rate_hz / 1e3:.0f} kHz, {mean_w:.0f} words and "
                          f"{mean_c:.0f} combinations per event on average",
-                slots=n_slots, max_events_per_batch=max_events, batched=batched, plain=plain)
+                slots=n_slots, max_events_per_batch=max_events,
+                batched_io="words read and results written in place in page-locked host "
+                           "memory (no copy calls); batched_copy: H2D and two-step D2H copies",
+                batched=out["mapped"], batched_copy=out["copy"], plain=plain)
 
 
 def measure_transfer(bank, tune, reps, workers):

@@ -186,7 +186,7 @@ svt_status svt_select(const svt_config *cfg, const svt_roads *roads, int64_t n_r
 /* The whole path in one pass (sections II and II-A: unpack, combine, fit, plus the chi-square
  * selection).  A single-pass pre-pass reads every word once and writes the road table, the
  * layer-grouped coordinates and each road's combination range (one kernel: decoupled look-back
- * over blocks of 4096 words).  A persistent fused kernel then takes tiles of tile_combos
+ * over blocks of 2048 words).  A persistent fused kernel then takes tiles of tile_combos
  * consecutive combinations, stages the roads' hits and constants in LDS, fits every combination
  * with integer VALU arithmetic and writes the same records, accept flags, road table and best
  * tracks as stages 1-4 (bit for bit).  The word count is read on the device from *d_n_words, so
@@ -234,6 +234,22 @@ svt_status svt_copy_async(void *dst, const void *src, int64_t bytes, int32_t kin
                           hipStream_t stream);
 svt_status svt_event_record(hipEvent_t event, hipStream_t stream);
 int32_t svt_event_done(hipEvent_t event);
+
+/* The results of one batch gathered into one buffer, for host loops that read them with no
+ * copy call (the serving form: `out` is then the device address of page-locked host memory from
+ * svt_mapped_pointer; device memory works as well).  Writes the header int64[8] = {*d_n_words,
+ * *d_n_roads, *d_n_combos, *d_n_kept (-1 when d_n_kept is NULL), *d_err, 0, 0, 0}; then, when
+ * 0 <= n_roads <= min(out_roads, road_cap), the first n_roads entries of best->chi2 (int64),
+ * then those of best->n_accept, best->k, best->p0, best->p1, best->p2, roads->event and
+ * roads->set (int32 each), back to back; otherwise the header only.  out must be 8-byte aligned
+ * and hold 64 + 36 * out_roads bytes; out_roads >= 0.  Values written to host memory are
+ * visible to the host once work enqueued after this call has completed (an event recorded
+ * after it).  SVT_ERR_ARG for NULL pointers (except d_n_kept) or a bad size. */
+svt_status svt_gather_results(const svt_roads *roads, const svt_best *best, int64_t road_cap,
+                              const int64_t *d_n_words, const int64_t *d_n_roads,
+                              const int64_t *d_n_combos, const int64_t *d_n_kept,
+                              const uint64_t *d_err, void *out, int64_t out_roads,
+                              hipStream_t stream);
 
 /* Destroy every cached graph (call before freeing buffers a cached graph refers to). */
 void svt_release_graphs(void);

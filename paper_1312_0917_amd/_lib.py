@@ -91,6 +91,8 @@ def load():
         "svt_copy_async": (_I32, [_P, _P, _I64, _I32, _P]),
         "svt_event_record": (_I32, [_P, _P]),
         "svt_event_done": (_I32, [_P]),
+        "svt_gather_results": (_I32, [S(svt_roads), S(svt_best), _I64, _P, _P, _P, _P, _P, _P,
+                                      _I64, _P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -105,7 +107,8 @@ def exported_symbols():
             "svt_combine_workspace", "svt_select_workspace", "svt_batch_workspace", "svt_unpack",
             "svt_combine", "svt_fit", "svt_select", "svt_process_batch",
             "svt_set_fused_timing_events", "svt_release_graphs", "svt_tune_resolve",
-            "svt_mapped_pointer", "svt_copy_async", "svt_event_record", "svt_event_done"]
+            "svt_mapped_pointer", "svt_copy_async", "svt_event_record", "svt_event_done",
+            "svt_gather_results"]
 
 
 # ---- marshalling helpers -----------------------------------------------------------------
@@ -268,6 +271,46 @@ class PreparedBatch:
 
     def __call__(self, words, flags, stream) -> int:
         return self._fn(*self._head, _ptr(words), *self._tail, flags, _stream(stream))
+
+
+GATHER_HEADER_BYTES = 64
+GATHER_BYTES_PER_ROAD = 36
+
+
+class PreparedGather:
+    """svt_gather_results for a fixed set of buffers: the header and the first n_roads per-road
+    results of a batch, written back to back into ``out`` (device memory, or the device address
+    of page-locked host memory) with one foreign call per batch."""
+
+    def __init__(self, roads, best, road_cap, d_n_words, d_n_roads, d_n_combos, d_n_kept, d_err,
+                 out, out_roads):
+        self._keep = (roads_struct(roads), best_struct(best))
+        r, b = self._keep
+        self._args = (ctypes.byref(r), ctypes.byref(b), road_cap, _ptr(d_n_words), _ptr(d_n_roads),
+                      _ptr(d_n_combos), _ptr(d_n_kept), _ptr(d_err), _ptr(out), out_roads)
+        self._fn = load().svt_gather_results
+
+    def __call__(self, stream):
+        check(self._fn(*self._args, _stream(stream)), "svt_gather_results")
+
+
+def gathered(buf: np.ndarray):
+    """Views into a buffer written by svt_gather_results (uint8 array, 8-byte aligned): the
+    header dict and, when the per-road part was written, a dict of per-road arrays."""
+    head = buf[:GATHER_HEADER_BYTES].view(np.int64)
+    h = dict(n_words=int(head[0]), n_roads=int(head[1]), n_combos=int(head[2]),
+             n_kept=int(head[3]), err=int(head[4]) & SVT_NO_ERROR)
+    nr = h["n_roads"]
+    cap = (len(buf) - GATHER_HEADER_BYTES) // GATHER_BYTES_PER_ROAD
+    if not 0 <= nr <= cap:
+        return h, None
+    off = GATHER_HEADER_BYTES
+    out = {"chi2": buf[off:off + 8 * nr].view(np.int64)}
+    off += 8 * nr
+    for k in ("n_accept", "k", "p0", "p1", "p2", "event", "set"):
+        out[k] = buf[off:off + 4 * nr].view(np.int32)
+        off += 4 * nr
+    return h, out
 
 
 def svt_set_fused_timing_events(start, stop):

@@ -10,6 +10,14 @@
 
 #include "svt_common.h"
 
+namespace svt {
+// launcher of k_gather (svt_stages.hip), used by svt_gather_results only
+hipError_t launch_gather(const svt_roads &roads, const svt_best &best, int64_t road_cap,
+                         const int64_t *d_n_words, const int64_t *d_n_roads,
+                         const int64_t *d_n_combos, const int64_t *d_n_kept,
+                         const uint64_t *d_err, void *out, int64_t out_roads, hipStream_t s);
+}  // namespace svt
+
 using namespace svt;
 
 namespace {
@@ -158,6 +166,24 @@ svt_status svt_mapped_pointer(void *host, void **dev) {
     if (!host || !dev) return SVT_ERR_ARG;
     *dev = nullptr;
     return hipHostGetDevicePointer(dev, host, 0) == hipSuccess && *dev ? SVT_OK : SVT_ERR_HIP;
+}
+
+svt_status svt_gather_results(const svt_roads *roads, const svt_best *best, int64_t road_cap,
+                              const int64_t *d_n_words, const int64_t *d_n_roads,
+                              const int64_t *d_n_combos, const int64_t *d_n_kept,
+                              const uint64_t *d_err, void *out, int64_t out_roads,
+                              hipStream_t stream) {
+    if (!roads || !best || !d_n_words || !d_n_roads || !d_n_combos || !d_err || !out)
+        return SVT_ERR_ARG;
+    if (!roads->event || !roads->set || !best->n_accept || !best->k || !best->p0 || !best->p1 ||
+        !best->p2 || !best->chi2)
+        return SVT_ERR_ARG;
+    if (road_cap < 0 || out_roads < 0 || out_roads > (INT64_MAX - 64) / 36) return SVT_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(out) % 8 != 0) return SVT_ERR_ARG;
+    return launch_gather(*roads, *best, road_cap, d_n_words, d_n_roads, d_n_combos, d_n_kept, d_err,
+                         out, out_roads, stream) == hipSuccess
+               ? SVT_OK
+               : SVT_ERR_HIP;
 }
 
 svt_status svt_tune_resolve(const svt_tune *tune, svt_tune *out) {

@@ -661,6 +661,35 @@ __global__ __launch_bounds__(kSegThreads) void k_kept_refit(
     }
 }
 
+// The header and the first n_roads per-road results of a batch, back to back in one buffer
+// (layout in svt_gather_results).  When the buffer is host memory every store crosses the bus
+// once; the closing system-scope fence makes them visible to the host with the kernel's end.
+__global__ void k_gather(svt_roads roads, svt_best best, int64_t road_cap, const int64_t *n_words,
+                         const int64_t *n_roads, const int64_t *n_combos, const int64_t *n_kept,
+                         const uint64_t *err, int64_t *out, int64_t out_roads) {
+    const int64_t nr = *n_roads;
+    if (gtid() == 0) {
+        out[0] = *n_words;
+        out[1] = nr;
+        out[2] = *n_combos;
+        out[3] = n_kept ? *n_kept : -1;
+        out[4] = static_cast<int64_t>(*err);
+        out[5] = out[6] = out[7] = 0;
+    }
+    if (nr >= 0 && nr <= out_roads && nr <= road_cap) {
+        int64_t *chi2 = out + 8;
+        int32_t *col = reinterpret_cast<int32_t *>(chi2 + nr);
+        const int32_t *src[7] = {best.n_accept, best.k, best.p0, best.p1, best.p2, roads.event,
+                                 roads.set};
+        for (int64_t i = gtid(); i < nr; i += gstride()) {
+            chi2[i] = best.chi2[i];
+#pragma unroll
+            for (int a = 0; a < 7; ++a) col[a * nr + i] = src[a][i];
+        }
+    }
+    __threadfence_system();
+}
+
 inline int64_t clamp_grid(int64_t blocks, int64_t maxb) {
     if (blocks < 1) return 1;
     return blocks < maxb ? blocks : maxb;
@@ -788,6 +817,17 @@ hipError_t launch_kept_write(const uint8_t *accept, Sizes n_combos, int64_t grid
     const int64_t g = clamp_grid(grid_blocks, 1 << 16);
     hipLaunchKernelGGL(k_kept_write, dim3(g), dim3(kSegThreads), 0, s, accept, n_combos,
                        kb_prefix, kept, kept_cap, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const svt_roads &roads, const svt_best &best, int64_t road_cap,
+                         const int64_t *d_n_words, const int64_t *d_n_roads,
+                         const int64_t *d_n_combos, const int64_t *d_n_kept,
+                         const uint64_t *d_err, void *out, int64_t out_roads, hipStream_t s) {
+    const int64_t g = clamp_grid((out_roads + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, s, roads, best, road_cap, d_n_words,
+                       d_n_roads, d_n_combos, d_n_kept, d_err, static_cast<int64_t *>(out),
+                       out_roads);
     return hipGetLastError();
 }
 

@@ -186,9 +186,12 @@ class BatchRunner:
 
     def __init__(self, cfg: L.svt_config, bank: torch.Tensor, word_cap: int, road_cap: int,
                  combo_cap: int, kept_cap: int = 0, tune: Optional[L.svt_tune] = None,
-                 graph=True, with_c=True, device="cuda", stream=None, kept_only=False):
+                 graph=True, with_c=True, device="cuda", stream=None, kept_only=False,
+                 n_words_ptr: Optional[int] = None):
         """``kept_only``: no per-combination records; ``rec`` then holds the fit values of the
-        accepted combinations, compacted in the order of the kept list (needs kept_cap > 0)."""
+        accepted combinations, compacted in the order of the kept list (needs kept_cap > 0).
+        ``n_words_ptr``: device address the kernels read the word count from (for instance
+        mapped host memory the caller writes), instead of the runner's own device word."""
         if kept_only and kept_cap <= 0:
             raise ValueError("kept-only mode needs a kept list (kept_cap > 0)")
         self.kept_only = kept_only
@@ -214,7 +217,8 @@ class BatchRunner:
         if nbytes < 0:
             raise ValueError("unsupported tune / capacities")
         self.work = _ws(nbytes, d)
-        self._call = L.PreparedBatch(self.bank, self.cfg, self.tune, self.d_n[0:1], self.word_cap,
+        d_n_words = self.d_n[0:1] if n_words_ptr is None else n_words_ptr
+        self._call = L.PreparedBatch(self.bank, self.cfg, self.tune, d_n_words, self.word_cap,
                                      self.roads, self.road_cap, self.rec, self.accept,
                                      self.combo_cap, self.best, self.kept, self.kept_cap,
                                      self.d_n[1:2], self.d_n[2:3],

@@ -17,6 +17,7 @@ the same methods.
 from __future__ import annotations
 
 import dataclasses
+import gc
 import time
 from collections import deque
 from typing import Callable, List, Optional, Sequence
@@ -49,6 +50,9 @@ class ServeStats:
     n_combos: int
     wall_s: float
     retries: int = 0
+    max_loop_gap_s: float = 0.0   # longest time between two passes of the host loop
+    max_service_s: float = 0.0    # longest launch-to-done time of one batch
+    max_service_batch: int = 0    # events in that batch
 
     def percentile_us(self, q) -> float:
         return float(np.percentile(self.latency_s, q) * 1e6)
@@ -62,7 +66,10 @@ class ServeStats:
                     batches=len(self.batch_sizes),
                     mean_batch=round(float(np.mean(self.batch_sizes)), 2),
                     combos_per_s=self.n_combos / self.wall_s if self.wall_s > 0 else 0.0,
-                    retries=self.retries)
+                    retries=self.retries,
+                    max_loop_gap_us=round(self.max_loop_gap_s * 1e6, 2),
+                    max_service_us=round(self.max_service_s * 1e6, 2),
+                    max_service_batch=self.max_service_batch)
 
 
 def serve(stream: EventStream, slots: Sequence, max_events: int = 256,
@@ -73,26 +80,47 @@ def serve(stream: EventStream, slots: Sequence, max_events: int = 256,
     A slot provides: ``fits(n_words, n_events) -> bool``, ``launch(words, e0, e1)``,
     ``poll() -> bool`` (finished), ``collect() -> (n_combos, per_event_results or None)``.
     """
+    # A full garbage collection of a large process heap takes milliseconds and would land in
+    # the latency of whatever batch it interrupts: collect once now and keep the collector off
+    # for the duration of the stream.
+    gc_on = gc.isenabled()
+    gc.collect()
+    gc.disable()
+    try:
+        return _serve(stream, slots, max_events, clock, keep_results, idle_sleep_s)
+    finally:
+        if gc_on:
+            gc.enable()
+
+
+def _serve(stream, slots, max_events, clock, keep_results, idle_sleep_s):
     n = stream.n_events
     lat = np.full(n, np.nan)
     results = [None] * n if keep_results else None
     fifo = deque()
     nxt = 0
-    busy = {}  # slot index -> (e0, e1)
+    busy = {}  # slot index -> (e0, e1, launch time)
     batch_sizes = []
     total_combos = 0
     done = 0
+    max_gap = max_service = 0.0
+    max_service_batch = 0
     t0 = clock()
+    prev = 0.0
     while done < n:
         now = clock() - t0
+        max_gap = max(max_gap, now - prev)
+        prev = now
         while nxt < n and stream.arrival_s[nxt] <= now:
             fifo.append(nxt)
             nxt += 1
         progressed = False
         for si in list(busy):
             if slots[si].poll():
-                e0, e1 = busy.pop(si)
+                e0, e1, t_launch = busy.pop(si)
                 t_done = clock() - t0
+                if t_done - t_launch > max_service:
+                    max_service, max_service_batch = t_done - t_launch, e1 - e0
                 nc, per_event = slots[si].collect()
                 total_combos += nc
                 lat[e0:e1] = t_done - stream.arrival_s[e0:e1]
@@ -115,7 +143,7 @@ def serve(stream: EventStream, slots: Sequence, max_events: int = 256,
             for _ in range(e1 - e0):
                 fifo.popleft()
             slot.launch(stream.slice(e0, e1), e0, e1)
-            busy[si] = (e0, e1)
+            busy[si] = (e0, e1, clock() - t0)
             batch_sizes.append(e1 - e0)
             progressed = True
         if not progressed:
@@ -128,7 +156,9 @@ def serve(stream: EventStream, slots: Sequence, max_events: int = 256,
                 time.sleep(idle_sleep_s)
     wall = clock() - t0
     stats = ServeStats(latency_s=lat, batch_sizes=batch_sizes, n_combos=total_combos, wall_s=wall,
-                       retries=sum(getattr(s, "retries", 0) for s in slots))
+                       retries=sum(getattr(s, "retries", 0) for s in slots),
+                       max_loop_gap_s=max_gap, max_service_s=max_service,
+                       max_service_batch=max_service_batch)
     return stats, results
 
 
@@ -139,45 +169,70 @@ def split_by_event(road_event: np.ndarray, arrays: dict, n_events: int) -> list:
 
 
 class GpuSlot:
-    """Fused persistent pass on its own stream: pinned words -> H2D -> graph replay -> D2H.
+    """Fused persistent pass on its own stream, one batch at a time.
 
-    Results come back in two steps so that only what the batch produced crosses PCIe: the
-    sizes and error word first (one 40-byte copy), then, once they are on the host, exactly
-    n_roads entries of the per-road best tracks, their event ordinals and constant sets.  Every
-    step is a single foreign call (prepared batch arguments, library copy and event helpers),
-    so that the host loop's cost per batch stays small next to the arrival gaps.
+    ``io="mapped"`` (default): nothing is copied by a runtime call.  The slot writes the word
+    count and the words into one page-locked buffer that the kernels read in place over the
+    bus, and one small gather kernel (svt_gather_results) writes the sizes, the error word and
+    the batch's n_roads per-road results straight into a second page-locked buffer.  A batch
+    is then one graph replay, one gather launch and one event: the runtime's copy calls, which
+    now and then spend milliseconds of host time inside the runtime, are off the loop.
+
+    ``io="copy"``: pinned words -> H2D -> graph replay -> D2H in two steps (the sizes and error
+    word first, then exactly n_roads entries of each per-road array), kept for comparison.
     """
 
     BEST_KEYS = ("n_accept", "k", "p0", "p1", "p2", "chi2")
+    IN_HEADER = 256  # bytes before the words in the mapped input buffer (word count first)
 
     def __init__(self, cfg, bank, word_cap: int, road_cap: int, combo_cap: int, tune=None,
-                 graph: bool = True, keep_results: bool = False):
+                 graph: bool = True, keep_results: bool = False, io: str = "mapped"):
         import torch
 
         from . import _lib as L
         from . import pipeline as P
 
-        self.torch, self.L = torch, L
-        self.runner = P.BatchRunner(cfg, bank, word_cap, road_cap, combo_cap, kept_cap=0,
-                                    tune=tune, graph=graph, with_c=False)
-        self.stream = self.runner.stream
+        if io not in ("mapped", "copy"):
+            raise ValueError(f"unknown io mode {io}")
+        self.torch, self.L, self.io = torch, L, io
         self.word_cap, self.road_cap, self.combo_cap = word_cap, road_cap, combo_cap
         self.keep = keep_results
-        self.h_words = torch.empty(word_cap, dtype=torch.int32, pin_memory=True)
-        self.h_words_np = self.h_words.numpy().view(np.uint32)
-        self.h_n = torch.empty(1, dtype=torch.int64, pin_memory=True)
-        self.h_n_np = self.h_n.numpy()
-        self.h_state = torch.empty(5, dtype=torch.int64, pin_memory=True)  # sizes[4], error
-        self.h_state_np = self.h_state.numpy()
-        self.h_best = {k: torch.empty(road_cap, dtype=v.dtype, pin_memory=True)
-                       for k, v in self.runner.best.items()}
-        self.h_event = torch.empty(road_cap, dtype=torch.int32, pin_memory=True)
-        self.h_set = torch.empty(road_cap, dtype=torch.int32, pin_memory=True)
-        # (device array, host array, element size) of the per-road results
-        self._fetch = [(self.runner.best[k], self.h_best[k], self.h_best[k].element_size())
-                       for k in self.BEST_KEYS]
-        self._fetch += [(self.runner.roads["event"], self.h_event, 4),
-                        (self.runner.roads["set"], self.h_set, 4)]
+        if io == "mapped":
+            self.h_in = torch.empty(self.IN_HEADER + 4 * word_cap, dtype=torch.uint8,
+                                    pin_memory=True)
+            h_in = self.h_in.numpy()
+            self.h_n_np = h_in[:8].view(np.int64)
+            self.h_words_np = h_in[self.IN_HEADER:].view(np.uint32)
+            d_in = L.svt_mapped_pointer(self.h_in)
+            self.d_words = d_in + self.IN_HEADER
+            self.runner = P.BatchRunner(cfg, bank, word_cap, road_cap, combo_cap, kept_cap=0,
+                                        tune=tune, graph=graph, with_c=False, n_words_ptr=d_in)
+            self.h_out = torch.empty(L.GATHER_HEADER_BYTES + L.GATHER_BYTES_PER_ROAD * road_cap,
+                                     dtype=torch.uint8, pin_memory=True)
+            self.h_out_np = self.h_out.numpy()
+            r = self.runner
+            self._gather = L.PreparedGather(r.roads, r.best, road_cap, d_in, r.d_n[1:2],
+                                            r.d_n[2:3], None, r.d_err,
+                                            L.svt_mapped_pointer(self.h_out), road_cap)
+        else:
+            self.runner = P.BatchRunner(cfg, bank, word_cap, road_cap, combo_cap, kept_cap=0,
+                                        tune=tune, graph=graph, with_c=False)
+            self.h_words = torch.empty(word_cap, dtype=torch.int32, pin_memory=True)
+            self.h_words_np = self.h_words.numpy().view(np.uint32)
+            self.h_n = torch.empty(1, dtype=torch.int64, pin_memory=True)
+            self.h_n_np = self.h_n.numpy()
+            self.h_state = torch.empty(5, dtype=torch.int64, pin_memory=True)  # sizes, error
+            self.h_state_np = self.h_state.numpy()
+            self.h_best = {k: torch.empty(road_cap, dtype=v.dtype, pin_memory=True)
+                           for k, v in self.runner.best.items()}
+            self.h_event = torch.empty(road_cap, dtype=torch.int32, pin_memory=True)
+            self.h_set = torch.empty(road_cap, dtype=torch.int32, pin_memory=True)
+            # (device array, host array, element size) of the per-road results
+            self._fetch = [(self.runner.best[k], self.h_best[k], self.h_best[k].element_size())
+                           for k in self.BEST_KEYS]
+            self._fetch += [(self.runner.roads["event"], self.h_event, 4),
+                            (self.runner.roads["set"], self.h_set, 4)]
+        self.stream = self.runner.stream
         self.sizes_ev = torch.cuda.Event()
         self.done_ev = torch.cuda.Event()
         for ev in (self.sizes_ev, self.done_ev):  # create the events
@@ -186,6 +241,8 @@ class GpuSlot:
         self.retries = 0
         self.batch = None
         self.stage = 0  # 1: sizes in flight, 2: results in flight, 3: complete
+        self._head = None
+        self._roads = None
 
     def fits(self, n_words: int, n_events: int) -> bool:
         # every road holds at least one word; combinations are checked on the device and a
@@ -197,6 +254,12 @@ class GpuSlot:
         n = len(words)
         self.h_words_np[:n] = words
         self.h_n_np[0] = n
+        if self.io == "mapped":
+            r.run(words=self.d_words)
+            self._gather(s)
+            L.svt_event_record(self.done_ev, s)
+            self.stage = 2
+            return
         L.svt_copy_async(r.d_n, self.h_n, 8, L.SVT_COPY_H2D, s)
         L.svt_copy_async(r.words, self.h_words, 4 * n, L.SVT_COPY_H2D, s)
         r.run()
@@ -204,9 +267,17 @@ class GpuSlot:
         L.svt_event_record(self.sizes_ev, s)
         self.stage = 1
 
+    def _sizes_err(self):
+        """[n_words, n_roads, n_combos, n_kept] and the raw error word of the finished batch."""
+        if self.io == "mapped":
+            h = self._head
+            return [h["n_words"], h["n_roads"], h["n_combos"], h["n_kept"]], h["err"]
+        v = self.h_state_np
+        return [int(x) for x in v[:4]], int(v[4]) & self.L.SVT_NO_ERROR
+
     def _error(self):
         L = self.L
-        err = int(self.h_state_np[4]) & L.SVT_NO_ERROR
+        err = self._sizes_err()[1]
         return L.error_decode(err) if err != L.SVT_NO_ERROR else (0, -1)
 
     def poll(self) -> bool:
@@ -226,6 +297,8 @@ class GpuSlot:
         if self.stage == 2:
             if not L.svt_event_done(self.done_ev):
                 return False
+            if self.io == "mapped":
+                self._head, self._roads = L.gathered(self.h_out_np)
             self.stage = 3
         return self.stage == 3
 
@@ -238,11 +311,20 @@ class GpuSlot:
         self.batch = (words, e0, e1)
         self._enqueue(words)
 
+    def _road_arrays(self, nr):
+        """Per-road results of the finished batch (copies: the host buffers are reused)."""
+        if self.io == "mapped":
+            return {k: v.copy() for k, v in self._roads.items()}
+        arrays = {k: self.h_best[k][:nr].numpy().copy() for k in self.BEST_KEYS}
+        arrays["event"] = self.h_event[:nr].numpy().copy()
+        arrays["set"] = self.h_set[:nr].numpy().copy()
+        return arrays
+
     def collect(self):
         L = self.L
         words, e0, e1 = self.batch
         st, idx = self._error()
-        sizes = [int(v) for v in self.h_state_np[:4]]
+        sizes, _ = self._sizes_err()
         if st == L.SVT_ERR_CAPACITY and e1 - e0 > 1:
             # more roads or combinations than this slot holds: split at an event boundary
             # and run the halves synchronously (rare when slots are sized for the stream)
@@ -252,10 +334,9 @@ class GpuSlot:
             raise RuntimeError(f"batch {e0}-{e1}: {L.status_name(st)} at {idx}")
         per_event = None
         if self.keep:
-            nr = sizes[1]
-            arrays = {k: self.h_best[k][:nr].numpy().copy() for k in self.BEST_KEYS}
-            arrays["set"] = self.h_set[:nr].numpy().copy()
-            per_event = split_by_event(self.h_event[:nr].numpy(), arrays, e1 - e0)
+            arrays = self._road_arrays(sizes[1])
+            road_event = arrays.pop("event")
+            per_event = split_by_event(road_event, arrays, e1 - e0)
         return sizes[2], per_event
 
     def _split_run(self, words, e0, e1):

@@ -6,6 +6,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1312_0917_amd import _lib as L
@@ -95,6 +96,37 @@ def test_host_argument_checks_reject_without_launching():
                                  ctypes.byref(roads), 0, ctypes.byref(rec), None, 0,
                                  ctypes.byref(best), None, 0, None, None, None, None, None, 0,
                                  0, None) == L.SVT_ERR_ARG
+    # svt_gather_results: null structs or arrays, a negative size, a misaligned buffer (the
+    # non-null "device" addresses are never dereferenced on the host)
+    fake = 1 << 20
+    full_roads = L.svt_roads(*([fake] * 6))
+    full_best = L.svt_best(*([fake] * 6))
+    ok_args = [ctypes.byref(full_roads), ctypes.byref(full_best), 10, fake, fake, fake, None,
+               fake, fake, 10, None]
+    for i, bad_v in [(0, None), (1, ctypes.byref(best)), (3, None), (7, None), (8, None),
+                     (8, fake + 4), (9, -1), (2, -1)]:
+        args = list(ok_args)
+        args[i] = bad_v
+        assert lib.svt_gather_results(*args) == L.SVT_ERR_ARG, i
+
+
+def test_gathered_layout_parses_header_and_road_arrays():
+    nr, cap = 3, 5
+    buf = np.zeros(L.GATHER_HEADER_BYTES + L.GATHER_BYTES_PER_ROAD * cap, dtype=np.uint8)
+    buf[:40].view(np.int64)[:] = [100, nr, 17, -1, -1]
+    off = L.GATHER_HEADER_BYTES
+    buf[off:off + 8 * nr].view(np.int64)[:] = [5, 7, 2 ** 40]
+    off += 8 * nr
+    for a in range(7):
+        buf[off:off + 4 * nr].view(np.int32)[:] = np.arange(nr) + 10 * a
+        off += 4 * nr
+    head, roads = L.gathered(buf)
+    assert head == dict(n_words=100, n_roads=nr, n_combos=17, n_kept=-1, err=L.SVT_NO_ERROR)
+    assert roads["chi2"].tolist() == [5, 7, 2 ** 40]
+    for a, k in enumerate(("n_accept", "k", "p0", "p1", "p2", "event", "set")):
+        assert roads[k].tolist() == [10 * a, 10 * a + 1, 10 * a + 2], k
+    buf[8:16].view(np.int64)[0] = cap + 1  # more roads than the buffer holds: header only
+    assert L.gathered(buf)[1] is None
 
 
 def test_product_path_does_not_import_the_oracle():

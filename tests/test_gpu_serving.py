@@ -32,13 +32,14 @@ def _alone_gpu(st, e, bank, dbank, cfg):
     return {k: to_np(out["best_" + k]) for k in KEYS}, ref
 
 
-def test_each_event_same_alone_and_in_the_mix(bank):
+@pytest.mark.parametrize("io", ["mapped", "copy"])
+def test_each_event_same_alone_and_in_the_mix(bank, io):
     cfg = oracle.make_config()
     dbank = P.device_bank(bank.f, bank.q)
     st = _stream(bank, 400, rate_hz=2e6)
     words_cap = 64 * 6000
     slots = [serve.GpuSlot(gpu_cfg(cfg), dbank, words_cap, words_cap // 5, 64 * 40000,
-                           keep_results=True) for _ in range(3)]
+                           keep_results=True, io=io) for _ in range(3)]
     stats, res = serve.serve(st, slots, max_events=64, keep_results=True)
     assert max(stats.batch_sizes) > 1, "the stream should have been batched"
     assert not np.isnan(stats.latency_s).any() and np.all(stats.latency_s > 0)
@@ -50,12 +51,14 @@ def test_each_event_same_alone_and_in_the_mix(bank):
     L.svt_release_graphs()
 
 
-def test_overflowing_batch_is_split_and_rerun(bank):
+@pytest.mark.parametrize("io", ["mapped", "copy"])
+def test_overflowing_batch_is_split_and_rerun(bank, io):
     cfg = oracle.make_config()
     dbank = P.device_bank(bank.f, bank.q)
     st = _stream(bank, 60, rate_hz=1e7, seed=4)
     # combination capacity of about 6 events: 16-event batches must split
-    slot = serve.GpuSlot(gpu_cfg(cfg), dbank, 16 * 6000, 16 * 1200, 80000, keep_results=True)
+    slot = serve.GpuSlot(gpu_cfg(cfg), dbank, 16 * 6000, 16 * 1200, 80000, keep_results=True,
+                         io=io)
     stats, res = serve.serve(st, [slot], max_events=16, keep_results=True)
     assert slot.retries > 0
     for e in range(0, st.n_events, 5):
@@ -72,3 +75,42 @@ def test_plain_slot_serves_the_same_stream(bank):
     stats, _ = serve.serve(st, [serve.PlainSlot(gpu_cfg(cfg), dbank)], max_events=16)
     tot = oracle.count(st.words, cfg)[3]
     assert stats.n_combos == tot
+
+
+@pytest.mark.parametrize("where", ["device", "mapped"])
+def test_gather_results_matches_the_batch_outputs(bank, where):
+    """svt_gather_results: header = the batch's sizes and error word, then exactly n_roads
+    entries of the best tracks, event ordinals and sets (integers: bit-exact); a buffer too
+    small for the roads gets the header only."""
+    cfg = oracle.make_config()
+    dbank = P.device_bank(bank.f, bank.q)
+    s = synth.make_sample("c4", n_events=24, bank=bank)
+    ref = oracle.run(s.words, bank.f, bank.q, cfg, combos=False)
+    nr = ref["n_roads"]
+    r = P.BatchRunner(gpu_cfg(cfg), dbank, len(s.words), nr + 7, ref["n_combos"] + 4,
+                      graph=False, with_c=False)
+    out = r.load(P.words_tensor(s.words)).run().result()
+    for cap in (nr + 7, nr, nr - 1):
+        nbytes = L.GATHER_HEADER_BYTES + L.GATHER_BYTES_PER_ROAD * cap
+        if where == "device":
+            buf = torch.full((nbytes,), 0xA5, dtype=torch.uint8, device="cuda")
+            dst = buf
+        else:
+            buf = torch.full((nbytes,), 0xA5, dtype=torch.uint8, pin_memory=True)
+            dst = L.svt_mapped_pointer(buf)
+        g = L.PreparedGather(r.roads, r.best, r.road_cap, r.d_n[0:1], r.d_n[1:2], r.d_n[2:3],
+                             None, r.d_err, dst, cap)
+        g(r.stream)
+        r.stream.synchronize()
+        head, roads = L.gathered(buf.cpu().numpy() if where == "device" else buf.numpy())
+        assert head == dict(n_words=len(s.words), n_roads=nr, n_combos=ref["n_combos"],
+                            n_kept=-1, err=L.SVT_NO_ERROR)
+        if cap < nr:
+            assert roads is None
+            continue
+        for k in KEYS:
+            assert np.array_equal(roads[k], to_np(out["best_" + k])), (cap, k)
+            assert np.array_equal(roads[k], np.asarray(ref[ORA[k]])), (cap, k)
+        assert np.array_equal(roads["event"], to_np(out["road_event"]))
+        assert np.array_equal(roads["set"], to_np(out["road_set"]))
+    L.svt_release_graphs()
