@@ -239,7 +239,11 @@ struct Stage {
 
 struct Loader {
     int64_t t, tile_start, tile_end, r_next;
-    uint32_t ticket;  // lane 0: ticket of the next tile, fetched when this tile started
+    // lane 0: ticket of the next tile.  It is fetched once the tile's first chunk has arrived,
+    // not when the tile starts: memory results return in issue order, so a fetch issued
+    // first would hold up the chunk's loads behind the counter every workgroup hits at once.
+    uint32_t ticket;
+    bool need_ticket;
     // road-table entries of roads r_next + lane, loaded one chunk ahead
     bool pf;
     int64_t pcb, phb;
@@ -264,14 +268,15 @@ __device__ __forceinline__ void load_roads(const FArgs &a, Loader &L, int64_t n_
     L.pf = true;
 }
 
+// first_road: the tile's first road when already read (< 0: read it here)
 __device__ __forceinline__ void start_tile(const FArgs &a, Loader &L, int64_t n_tiles,
-                                           int64_t n_combos, int64_t T) {
+                                           int64_t n_combos, int64_t T, int64_t first_road = -1) {
     L.pf = false;
     if (L.t < n_tiles) {
         L.tile_start = L.t * T;
         L.tile_end = (L.tile_start + T < n_combos) ? L.tile_start + T : n_combos;
-        L.r_next = a.tile_first_road[L.t];
-        if (lane_id() == 0) L.ticket = atomicAdd(a.tile_counter, 1u);
+        L.r_next = first_road >= 0 ? first_road : a.tile_first_road[L.t];
+        L.need_ticket = true;
     }
 }
 
@@ -305,7 +310,11 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
         const int32_t wo = wend - nwords, to = tend - ntab;
         const bool fits = valid && wend <= kWordCap && tend <= kTabCap;  // a prefix of lanes
         const int nr = __popcll(__ballot(fits));
-        if (nr == 0) {  // tile finished: continue with the ticket fetched when it started
+        if (nr == 0) {  // tile finished: continue with the ticket fetched during it
+            if (L.need_ticket) {
+                if (lane == 0) L.ticket = atomicAdd(a.tile_counter, 1u);
+                L.need_ticket = false;
+            }
             const uint32_t tk = __shfl(L.ticket, 0);
             L.t = static_cast<int64_t>(gridDim.x) + tk;
             start_tile(a, L, n_tiles, n_combos, T);
@@ -357,6 +366,10 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
                 const int i = lane + 64 * u;
                 if (i < n16) dst[i] = v[u];
             }
+        }
+        if (L.need_ticket) {  // the chunk's loads are in: ask for the next tile now
+            if (lane == 0) L.ticket = atomicAdd(a.tile_counter, 1u);
+            L.need_ticket = false;
         }
         if (fits) {
             RoadMeta m;
@@ -740,10 +753,35 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG == 256 ? 
     static_assert(WG > kWaveSize, "one loader wave plus compute waves");
     __shared__ Stage S[2];
 
-    if (has_error(a.err)) return;
-    const int64_t n_roads = *a.d_n_roads;
-    const int64_t n_combos = *a.d_n_combos;
-    if (n_roads < 0 || n_roads > a.road_cap || n_combos < 0 || n_combos > a.combo_cap) return;
+    // The error word, the two sizes and the first road of this workgroup's first tile do not
+    // depend on each other: one vector load brings all of them, lanes 0-5 the 32-bit halves of
+    // the three 64-bit words and lane 6 the first road, so they share one round trip (as
+    // uniform scalar loads the compiler serialises them, one wait each).  Errors of the earlier
+    // kernels of the pass are what matters here, so a plain load of the error word suffices.
+    int64_t first_road, n_roads, n_combos;
+    uint64_t err0;
+    {
+        const int ln = lane_id();
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(a.err);
+        p = (ln == 2 || ln == 3) ? reinterpret_cast<const uint32_t *>(a.d_n_roads) : p;
+        p = (ln == 4 || ln == 5) ? reinterpret_cast<const uint32_t *>(a.d_n_combos) : p;
+        p = (ln == 6 && blockIdx.x < a.tiles_cap)
+                ? reinterpret_cast<const uint32_t *>(a.tile_first_road + blockIdx.x)
+                : p;
+        const int w = static_cast<int>(p[(ln < 6 && (ln & 1)) ? 1 : 0]);
+        auto word64 = [&](int l) {
+            return static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readlane(w, l))) |
+                   (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readlane(w, l + 1)))
+                    << 32);
+        };
+        err0 = word64(0);
+        n_roads = static_cast<int64_t>(word64(2));
+        n_combos = static_cast<int64_t>(word64(4));
+        first_road = blockIdx.x < a.tiles_cap ? __builtin_amdgcn_readlane(w, 6) : 0;
+    }
+    if ((err0 != SVT_NO_ERROR) | (n_roads < 0) | (n_roads > a.road_cap) | (n_combos < 0) |
+        (n_combos > a.combo_cap))
+        return;
     const int64_t T = a.tile_combos;
     const int64_t n_tiles = (n_combos + T - 1) / T;
     if (n_tiles > a.tiles_cap) return;
@@ -756,12 +794,13 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG == 256 ? 
     L.t = blockIdx.x;
     L.tile_start = L.tile_end = L.r_next = 0;
     L.ticket = 0;
+    L.need_ticket = false;
     L.pf = false;
     L.pcb = L.phb = 0;
     L.pC = L.ps = 0;
     L.pnh = 0;
     if (wave == 0) {
-        start_tile(a, L, n_tiles, n_combos, T);
+        start_tile(a, L, n_tiles, n_combos, T, first_road);
         produce(a, S[0], L, n_roads, n_combos, n_tiles, T, qlmask);
     }
     __syncthreads();
