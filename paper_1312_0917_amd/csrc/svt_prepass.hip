@@ -15,13 +15,19 @@
 //
 // Everything a block needs from its own words (road list, hits per layer, combinations,
 // grouped coordinates) is computed before it looks back, so the only wait is one look-back.
-// Blocks take ordered tickets, so a block only ever waits on blocks that started before it.
 // Two 64-bit status words per block carry the running counts -- roads and events packed in one
 // (31 bits each: a batch holds fewer than 2^31 words), combinations in the other: the top two
 // bits say "aggregate of this block" or "inclusive prefix up to this block", the rest hold the
-// value.  The status words are cleared by the batch-reset kernel before every pass.  Waits are
-// bounded: a look-back that does not finish within the bound reports an internal error and
-// still publishes, instead of spinning forever.
+// value.  The status words are cleared by the batch-reset kernel before every pass.
+//
+// Blocks are numbered by their index in the grid, with no ticket: every block fetching an
+// ordered ticket from one counter at the start serialises on that counter (about 12 ns per
+// block, 11 us for the last of 940 blocks).  A ticket would guarantee that a block only waits
+// on blocks already running; without it, a look-back round that has waited too long computes
+// the aggregates it is missing from the words themselves (block_aggregate), so no block can
+// wait forever on one that has not been scheduled, and the wait stays bounded.
+#include <cstdlib>
+
 #include "svt_common.h"
 
 namespace svt {
@@ -35,7 +41,9 @@ constexpr int kOff = 4;                   // sw[kOff - 1] = word before the bloc
 constexpr uint64_t kStAgg = 1ull << 62;
 constexpr uint64_t kStIncl = 2ull << 62;
 constexpr uint64_t kStMask = 3ull << 62;
-constexpr int kSpinLimit = 1 << 20;
+// a look-back round computes missing aggregates itself after this long (wall-clock ticks of
+// 10 ns): far beyond any wait on a predecessor that is running
+constexpr uint64_t kLookbackTimeout = 20000;
 constexpr int kLookWindows = 8;           // predecessors read per round: 64 per window
 
 __device__ inline void status_publish(int64_t *p, uint64_t v) {
@@ -43,9 +51,99 @@ __device__ inline void status_publish(int64_t *p, uint64_t v) {
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// publish v for a block that has published nothing yet (no effect otherwise)
+__device__ inline void status_claim(int64_t *p, uint64_t v) {
+    uint64_t expected = 0;
+    __hip_atomic_compare_exchange_strong(reinterpret_cast<uint64_t *>(p), &expected, v,
+                                         __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ inline uint64_t status_read(int64_t *p) {
     return __hip_atomic_load(reinterpret_cast<uint64_t *>(p), __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct PArgs {
+    const uint32_t *words;
+    Sizes nw;
+    svt_config cfg;
+    svt_roads roads;
+    int64_t road_cap;
+    int16_t *coords;
+    svt_best best;
+    int64_t tile_combos;
+    int32_t *tile_first_road;
+    int64_t tiles_cap;
+    int64_t combo_cap;
+    int64_t *d_n_roads;
+    int64_t *d_n_combos;
+    int64_t *status;  // [2][nb_cap]: roads | events << 31, combinations
+    int64_t nb_cap;
+    uint64_t lookback_timeout;  // wall-clock ticks a look-back waits before computing itself
+    uint64_t *err;
+    int32_t *event_first_road;
+    int64_t event_cap;
+    int64_t *d_n_events;
+};
+
+__device__ inline int64_t combos_of(uint32_t packed) {
+    int64_t c = 1;
+#pragma unroll
+    for (int l = 0; l < SVT_N_LAYERS; ++l) c *= nh_of(packed, l);
+    return c;
+}
+
+// The aggregate of block p -- roads that start among its words | events that start there << 31,
+// and the combinations of those roads -- computed from the words in global memory by the rules
+// block p applies to its own staged words (a road runs to the next road start among the block's
+// words and its 64-word tail, else to the end of them; longer than n_layers * max_hits words,
+// or more than max_hits hits on a layer, and it has no combinations).  A look-back that has
+// waited too long for block p to publish uses this instead, so that no block can wait forever
+// on one that has not been scheduled.  One wave; lane i takes the block's words 32 i .. 32 i + 31.
+__device__ void block_aggregate(const PArgs &a, int64_t n, int64_t p, uint64_t &agg0,
+                                uint64_t &agg1) {
+    constexpr int kPerLane = kPB / kWaveSize;
+    const int lane = lane_id();
+    const int64_t base = p * kPB;
+    const int nloc = static_cast<int>(n - base < kPB + kTail ? n - base : kPB + kTail);
+    const int nown = nloc < kPB ? nloc : kPB;
+    const int max_len = a.cfg.n_layers * a.cfg.max_hits;
+    int64_t nr = 0, ne = 0, nc = 0;
+    for (int e = 0; e < kPerLane; ++e) {
+        const int j = lane * kPerLane + e;
+        if (j >= nown) break;
+        const uint32_t x = a.words[base + j];
+        const bool first = base + j == 0;
+        const uint32_t px = first ? 0u : a.words[base + j - 1];
+        ne += (first || w_etag(x) != w_etag(px)) ? 1 : 0;
+        if (!(first || w_tags(x) != w_tags(px))) continue;
+        ++nr;
+        uint64_t cnt = 0;  // 8 bits per layer
+        bool over = false;
+        uint32_t prev = x;
+        for (int k = j, len = 0; k < nloc; ++k) {
+            const uint32_t y = a.words[base + k];
+            if (k > j && w_tags(y) != w_tags(prev)) break;  // next road starts
+            if (++len > max_len) {
+                over = true;
+                break;
+            }
+            const uint32_t l = w_layer(y);
+            if (l < SVT_N_LAYERS) cnt += 1ull << (8 * l);
+            prev = y;
+        }
+        uint32_t packed = 0;
+#pragma unroll
+        for (int l = 0; l < SVT_N_LAYERS; ++l) {
+            const uint32_t c = static_cast<uint32_t>((cnt >> (8 * l)) & 0xFF);
+            over |= c > static_cast<uint32_t>(a.cfg.max_hits);
+            packed |= (c & 0xFu) << (4 * l);
+        }
+        if (!over) nc += combos_of(packed);
+    }
+    agg0 = static_cast<uint64_t>(wave_sum(nr)) | (static_cast<uint64_t>(wave_sum(ne)) << 31);
+    agg1 = static_cast<uint64_t>(wave_sum(nc));
 }
 
 // Exclusive prefixes over blocks 0..b-1 of two status columns at once (col0[i], col1[i] =
@@ -54,9 +152,12 @@ __device__ inline uint64_t status_read(int64_t *p) {
 // round reads kLookWindows * 64 predecessors of both columns (lane i of window k inspects block
 // top - 64 k - i, so position 0 is the nearest predecessor); each column sums its values up to
 // its nearest block that already has an inclusive value.  Values are opaque sums: counts packed
-// in one word add field by field as long as no field overflows.
-__device__ void look_back2(int64_t *col0, int64_t *col1, int64_t b, uint64_t agg0,
-                           uint64_t agg1, uint64_t *err, uint64_t &ex0, uint64_t &ex1) {
+// in one word add field by field as long as no field overflows.  A round that has waited
+// a.lookback_timeout wall-clock ticks for predecessors to publish computes their aggregates
+// from the words instead (block_aggregate) and goes on.
+__device__ void look_back2(const PArgs &a, int64_t n, int64_t b, uint64_t agg0, uint64_t agg1,
+                           uint64_t &ex0, uint64_t &ex1) {
+    int64_t *col0 = a.status, *col1 = a.status + a.nb_cap;
     const int lane = lane_id();
     ex0 = 0;
     ex1 = 0;
@@ -73,7 +174,7 @@ __device__ void look_back2(int64_t *col0, int64_t *col1, int64_t b, uint64_t agg
     }
     bool done0 = false, done1 = false;
     int64_t top = b - 1;
-    int spins = 0;
+    uint64_t wait_since = 0;  // start of this round's wait (0: not waiting)
     while (!(done0 && done1)) {
         uint64_t v0[kLookWindows], v1[kLookWindows];
 #pragma unroll
@@ -98,14 +199,32 @@ __device__ void look_back2(int64_t *col0, int64_t *col1, int64_t b, uint64_t agg
                              ((v1[k] & kStMask) == 0 && pos <= f1)) != 0;
         }
         if (wait) {  // a block at or before a nearest inclusive one has not published yet
-            if (++spins > kSpinLimit) {  // never expected: give up, but still publish so
-                if (lane == 0)            // that the blocks after this one finish too
-                    report(err, SVT_ERRCLASS_INDEX, static_cast<uint64_t>(b));
-                break;
+            const uint64_t now = wall_clock64();
+            if (wait_since == 0) wait_since = now;
+            if (now - wait_since < a.lookback_timeout) {
+                __builtin_amdgcn_s_sleep(1);
+                continue;
             }
-            __builtin_amdgcn_s_sleep(1);
+            // Waited long enough: publish every aggregate this round still misses, computed
+            // from the words, then read the round again.  A compare-and-swap from "nothing"
+            // never overwrites what the block itself has published meanwhile (and what it
+            // publishes later is the same aggregate, or its inclusive prefix).
+            int need = (done0 ? -1 : f0) > (done1 ? -1 : f1) ? f0 : f1;  // farthest position
+            need = need < 64 * kLookWindows ? need : 64 * kLookWindows - 1;  // of this round
+            for (int64_t idx = top; idx >= 0 && top - idx <= need; --idx) {
+                const uint64_t s0 = status_read(col0 + idx), s1 = status_read(col1 + idx);
+                if ((s0 & kStMask) != 0 && (s1 & kStMask) != 0) continue;
+                uint64_t g0, g1;
+                block_aggregate(a, n, idx, g0, g1);
+                if (lane == 0) {
+                    status_claim(col0 + idx, kStAgg | g0);
+                    status_claim(col1 + idx, kStAgg | g1);
+                }
+            }
+            wait_since = 0;
             continue;
         }
+        wait_since = 0;
         uint64_t m0 = 0, m1 = 0;
 #pragma unroll
         for (int k = 0; k < kLookWindows; ++k) {
@@ -125,35 +244,6 @@ __device__ void look_back2(int64_t *col0, int64_t *col1, int64_t b, uint64_t agg
     }
 }
 
-struct PArgs {
-    const uint32_t *words;
-    Sizes nw;
-    svt_config cfg;
-    svt_roads roads;
-    int64_t road_cap;
-    int16_t *coords;
-    svt_best best;
-    int64_t tile_combos;
-    int32_t *tile_first_road;
-    int64_t tiles_cap;
-    int64_t combo_cap;
-    int64_t *d_n_roads;
-    int64_t *d_n_combos;
-    int64_t *status;  // [2][nb_cap]: roads | events << 31, combinations
-    int64_t nb_cap;
-    uint32_t *ticket;
-    uint64_t *err;
-    int32_t *event_first_road;
-    int64_t event_cap;
-    int64_t *d_n_events;
-};
-
-__device__ inline int64_t combos_of(uint32_t packed) {
-    int64_t c = 1;
-#pragma unroll
-    for (int l = 0; l < SVT_N_LAYERS; ++l) c *= nh_of(packed, l);
-    return c;
-}
 
 // Per owned road, in LDS: s_road[rl] = first local word (12 bits) | events started in the block
 // up to that word (12 bits) << 12 | the word starts an event << 24; s_info[rl] = hits per layer (4 bits each) | too-many-hits
@@ -168,14 +258,11 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
     __shared__ uint32_t s_info[kPB];
     __shared__ int64_t tmp[kPT / kWaveSize + 1];
     __shared__ int64_t s_pre[3];
-    __shared__ int64_t s_blk;
     __shared__ int32_t s_tail_end;
 
     const int tid = threadIdx.x;
-    if (tid == 0) s_blk = atomicAdd(a.ticket, 1u);
-    __syncthreads();
-    const int64_t b = s_blk;
     const int64_t n = load_size(a.nw);
+    const int64_t b = blockIdx.x;
     const int64_t nb = (n + kPB - 1) / kPB;
     if (b == 0 && tid == 0 && a.nw.dev && *a.nw.dev > a.nw.cap)
         report(a.err, SVT_ERRCLASS_CAPACITY, 3);
@@ -318,9 +405,8 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
     // stay below 2^31) ---------------------------------------------------------------------------
     if (tid < kWaveSize) {
         uint64_t p0, p1;
-        look_back2(a.status, a.status + a.nb_cap, b,
-                   static_cast<uint64_t>(tr) | (static_cast<uint64_t>(te) << 31),
-                   static_cast<uint64_t>(tc), a.err, p0, p1);
+        look_back2(a, n, b, static_cast<uint64_t>(tr) | (static_cast<uint64_t>(te) << 31),
+                   static_cast<uint64_t>(tc), p0, p1);
         if (tid == 0) {
             s_pre[0] = static_cast<int64_t>(p0 & 0x7FFFFFFFull);
             s_pre[1] = static_cast<int64_t>(p0 >> 31);
@@ -384,7 +470,8 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
     }
 }
 
-// Clears the error word, the two work tickets, the kept count and the look-back status words
+// Clears the error word, the work tickets (the fused kernel's tile counter is the first), the
+// kept count and the look-back status words
 // of the blocks this pass will use.
 __global__ void k_batch_reset(uint64_t *err, uint32_t *tickets, int64_t *d_n_kept,
                               int64_t *status, int64_t nb_cap, Sizes nw) {
@@ -422,7 +509,9 @@ hipError_t launch_prepass(const PrepassLaunch &p, hipStream_t s) {
     a.d_n_combos = p.d_n_combos;
     a.status = p.status;
     a.nb_cap = p.nb_cap;
-    a.ticket = p.tickets + 1;
+    a.lookback_timeout = kLookbackTimeout;
+    if (const char *e = std::getenv("SVT_LOOKBACK_TIMEOUT_TICKS"))  // test hook: 0 forces the
+        a.lookback_timeout = std::strtoull(e, nullptr, 10);        // computed aggregates
     a.err = p.err;
     a.event_first_road = p.event_first_road;
     a.event_cap = p.event_cap;
