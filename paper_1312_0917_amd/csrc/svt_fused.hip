@@ -239,9 +239,10 @@ struct Stage {
 
 struct Loader {
     int64_t t, tile_start, tile_end, r_next;
-    // lane 0: ticket of the next tile.  It is fetched once the tile's first chunk has arrived,
-    // not when the tile starts: memory results return in issue order, so a fetch issued
-    // first would hold up the chunk's loads behind the counter every workgroup hits at once.
+    // lane 0: ticket of the next tile, fetched only when there are more tiles than workgroups,
+    // and then once the tile's first chunk has arrived, not when the tile starts: memory
+    // results return in issue order, so a fetch issued first would hold up the chunk's loads
+    // behind the counter every workgroup hits at once.
     uint32_t ticket;
     bool need_ticket;
     // road-table entries of roads r_next + lane, loaded one chunk ahead
@@ -276,7 +277,8 @@ __device__ __forceinline__ void start_tile(const FArgs &a, Loader &L, int64_t n_
         L.tile_start = L.t * T;
         L.tile_end = (L.tile_start + T < n_combos) ? L.tile_start + T : n_combos;
         L.r_next = first_road >= 0 ? first_road : a.tile_first_road[L.t];
-        L.need_ticket = true;
+        // tiles past the grid exist only when there are more tiles than workgroups
+        L.need_ticket = n_tiles > static_cast<int64_t>(gridDim.x);
     }
 }
 
@@ -311,7 +313,8 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
         const bool fits = valid && wend <= kWordCap && tend <= kTabCap;  // a prefix of lanes
         const int nr = __popcll(__ballot(fits));
         if (nr == 0) {  // tile finished: continue with the ticket fetched during it
-            if (L.need_ticket) {
+            if (L.need_ticket) {  // (never set when no tile lies past the grid: the ticket then
+                                  // stays 0 and gridDim.x + 0 is past the last tile)
                 if (lane == 0) L.ticket = atomicAdd(a.tile_counter, 1u);
                 L.need_ticket = false;
             }
