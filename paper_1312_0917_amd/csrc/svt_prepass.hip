@@ -146,12 +146,22 @@ __device__ void block_aggregate(const PArgs &a, int64_t n, int64_t p, uint64_t &
     agg1 = static_cast<uint64_t>(wave_sum(nc));
 }
 
+// A block's own counts, published as soon as they are known: an aggregate, or for block 0
+// directly its inclusive prefix.  One thread.
+__device__ inline void publish_aggregate(const PArgs &a, int64_t b, uint64_t agg0,
+                                         uint64_t agg1) {
+    const uint64_t flag = b == 0 ? kStIncl : kStAgg;
+    status_publish(a.status + b, flag | agg0);
+    status_publish(a.status + a.nb_cap + b, flag | agg1);
+}
+
 // Exclusive prefixes over blocks 0..b-1 of two status columns at once (col0[i], col1[i] =
-// column 0 and 1 of block i).  Publishes this block's aggregates first and its inclusive
-// prefixes once known.  Executed by one whole wave; the results are valid in every lane.  One
-// round reads kLookWindows * 64 predecessors of both columns (lane i of window k inspects block
-// top - 64 k - i, so position 0 is the nearest predecessor); each column sums its values up to
-// its nearest block that already has an inclusive value.  Values are opaque sums: counts packed
+// column 0 and 1 of block i), for a block whose aggregates are already published
+// (publish_aggregate); publishes its inclusive prefixes once known.  Executed by one whole
+// wave; the results are valid in every lane.  One round reads kLookWindows * 64 predecessors
+// of both columns (lane i of window k inspects block top - 64 k - i, so position 0 is the
+// nearest predecessor); each column sums its values up to its nearest block that already has
+// an inclusive value.  Values are opaque sums: counts packed
 // in one word add field by field as long as no field overflows.  A round that has waited
 // a.lookback_timeout wall-clock ticks for predecessors to publish computes their aggregates
 // from the words instead (block_aggregate) and goes on.
@@ -161,17 +171,7 @@ __device__ void look_back2(const PArgs &a, int64_t n, int64_t b, uint64_t agg0, 
     const int lane = lane_id();
     ex0 = 0;
     ex1 = 0;
-    if (b == 0) {
-        if (lane == 0) {
-            status_publish(col0, kStIncl | agg0);
-            status_publish(col1, kStIncl | agg1);
-        }
-        return;
-    }
-    if (lane == 0) {
-        status_publish(col0 + b, kStAgg | agg0);
-        status_publish(col1 + b, kStAgg | agg1);
-    }
+    if (b == 0) return;  // its inclusive prefix is its aggregate, already published
     bool done0 = false, done1 = false;
     int64_t top = b - 1;
     uint64_t wait_since = 0;  // start of this round's wait (0: not waiting)
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
     }
     __syncthreads();
 
-    // ---- one road per thread: hits per layer, checks, grouped coordinates -------------------
+    // ---- one road per thread: hits per layer, checks, combinations --------------------------
     const int max_len = a.cfg.n_layers * a.cfg.max_hits;
     int64_t csum = 0;
     for (int rl = tid; rl < nroads; rl += kPT) {
@@ -368,45 +368,57 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
             }
         }
         uint32_t packed = 0;
-        uint32_t off[SVT_N_LAYERS];
-        uint32_t run = 0;
 #pragma unroll
         for (int l = 0; l < SVT_N_LAYERS; ++l) {
             const uint32_t c = static_cast<uint32_t>((cnt >> (8 * l)) & 0xFF);
             over |= c > static_cast<uint32_t>(a.cfg.max_hits);
             packed |= (c & 0xFu) << (4 * l);
-            off[l] = run;
-            run += c;
         }
-        if (!over) {
-            for (int i0 = 0; i0 < len; i0 += 8) {
-                uint32_t x[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) x[u] = i0 + u < len ? sw[kOff + j + i0 + u] : 0xE000u;
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const uint32_t l = w_layer(x[u]);
-                    if (l >= SVT_N_LAYERS) continue;
-                    uint32_t o = 0;
-#pragma unroll
-                    for (int k = 0; k < SVT_N_LAYERS; ++k)
-                        if (static_cast<uint32_t>(k) == l) { o = off[k]; off[k] = o + 1; }
-                    sc[j + o] = static_cast<int16_t>(w_coord(x[u]));
-                }
-            }
-            csum += combos_of(packed);
-        }
+        if (!over) csum += combos_of(packed);
         const bool noset = w_rtag(sw[kOff + j]) >= static_cast<uint32_t>(a.cfg.n_sets);
         s_info[rl] = packed | (over ? kInfoOver : 0u) | (noset ? kInfoSet : 0u);
     }
-    const int64_t tc = block_sum<int64_t, kPT>(csum, tmp);
+    const int64_t tc = block_sum<int64_t, kPT>(csum, tmp);  // (its barrier publishes s_info)
+    const uint64_t agg0 = static_cast<uint64_t>(tr) | (static_cast<uint64_t>(te) << 31);
+    const uint64_t agg1 = static_cast<uint64_t>(tc);
+    // the aggregate is all that later blocks need from this one: publish it before grouping
+    if (tid == 0) publish_aggregate(a, b, agg0, agg1);
+
+    // ---- grouped coordinates of the roads with combinations (while predecessors finish) ----
+    for (int rl = tid; rl < nroads; rl += kPT) {
+        const uint32_t info = s_info[rl];
+        if (info & kInfoOver) continue;
+        const int j = s_road[rl] & 0xFFF;
+        const int len = static_cast<int>(s_road[rl + 1] & 0xFFF) - j;
+        uint32_t off[SVT_N_LAYERS];
+        uint32_t run = 0;
+#pragma unroll
+        for (int l = 0; l < SVT_N_LAYERS; ++l) {
+            off[l] = run;
+            run += nh_of(info, l);
+        }
+        for (int i0 = 0; i0 < len; i0 += 8) {
+            uint32_t x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = i0 + u < len ? sw[kOff + j + i0 + u] : 0xE000u;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const uint32_t l = w_layer(x[u]);
+                if (l >= SVT_N_LAYERS) continue;
+                uint32_t o = 0;
+#pragma unroll
+                for (int k = 0; k < SVT_N_LAYERS; ++k)
+                    if (static_cast<uint32_t>(k) == l) { o = off[k]; off[k] = o + 1; }
+                sc[j + o] = static_cast<int16_t>(w_coord(x[u]));
+            }
+        }
+    }
 
     // ---- running counts of the blocks before this one (roads and events share a word: both
     // stay below 2^31) ---------------------------------------------------------------------------
     if (tid < kWaveSize) {
         uint64_t p0, p1;
-        look_back2(a, n, b, static_cast<uint64_t>(tr) | (static_cast<uint64_t>(te) << 31),
-                   static_cast<uint64_t>(tc), p0, p1);
+        look_back2(a, n, b, agg0, agg1, p0, p1);
         if (tid == 0) {
             s_pre[0] = static_cast<int64_t>(p0 & 0x7FFFFFFFull);
             s_pre[1] = static_cast<int64_t>(p0 >> 31);
