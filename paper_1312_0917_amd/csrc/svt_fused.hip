@@ -29,6 +29,7 @@ constexpr int kChunk = 64;             // roads staged per chunk: one loader lan
 constexpr int kWordCap = 2048;         // coordinates staged per chunk (a road has at most 40)
 constexpr int kTabCap = 2048;          // coordinate-pair table entries per chunk (<= 136/road)
 constexpr int kMapCap = kMaxTile / 4;  // groups of 4 combinations in a tile
+constexpr int kMaxLayerHits = SVT_MAX_HITS;  // hits on one layer of a road with combinations
 constexpr int kRecNone = 0;  // no per-combination records (kept-only output)
 constexpr int kRecFit = 1;   // p0..p2 and chi2
 constexpr int kRecRows = 2;  // also the constraint rows c0..c2 (each pointer may be null)
@@ -224,7 +225,9 @@ __device__ __forceinline__ void fit4(const RoadMeta &m, const RoadConst &c, int3
 
 // One staged chunk: up to 64 consecutive roads of a tile.
 struct Stage {
-    alignas(16) int16_t G[kWordCap + 32];  // layer-grouped coordinates (16-byte copy slack)
+    // layer-grouped coordinates; the slack covers the 16-byte copies (up to 7 words past the
+    // chunk's last) and the table build's reads of kMaxLayerHits words from a layer's start
+    alignas(16) int16_t G[kWordCap + 32];
     int32_t XT[kTabCap];                   // coordinate-pair tables
     uint8_t M[kMapCap];                    // group of 4 combinations -> road of its first one
     uint16_t X[kChunk];                    // groups that span a road boundary (from g_lo)
@@ -409,17 +412,33 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
                 const int32_t off1 = g0 + n0, off2 = off1 + n1, off3 = off2 + n2,
                               off4 = off3 + n3;
                 const int32_t b01 = to, b23 = to + n0 * n1, b4 = b23 + n2 * n3;
-                for (int32_t h0 = 0; h0 < n0; ++h0) {
+                // the hits of layers 1, 3 and 4 in registers first (a layer of a road with
+                // combinations holds at most kMaxLayerHits; reads past a layer stay inside
+                // G's slack), so that the table writes wait on no LDS read of their own
+                int32_t y1[kMaxLayerHits], y3[kMaxLayerHits], y4[kMaxLayerHits];
+#pragma unroll
+                for (int i = 0; i < kMaxLayerHits; ++i) {
+                    y1[i] = S.G[off1 + i];
+                    y3[i] = S.G[off3 + i];
+                    y4[i] = S.G[off4 + i];
+                }
+                int32_t t = b01;
+                for (int32_t h0 = 0; h0 < n0; ++h0, t += n1) {
                     const int32_t x0 = S.G[g0 + h0];
-                    for (int32_t h1 = 0; h1 < n1; ++h1)
-                        S.XT[b01 + h0 * n1 + h1] = pack16(x0, S.G[off1 + h1]);
+#pragma unroll
+                    for (int h1 = 0; h1 < kMaxLayerHits; ++h1)
+                        if (h1 < n1) S.XT[t + h1] = pack16(x0, y1[h1]);
                 }
-                for (int32_t h2 = 0; h2 < n2; ++h2) {
+                t = b23;
+                for (int32_t h2 = 0; h2 < n2; ++h2, t += n3) {
                     const int32_t x2 = S.G[off2 + h2];
-                    for (int32_t h3 = 0; h3 < n3; ++h3)
-                        S.XT[b23 + h2 * n3 + h3] = pack16(x2, S.G[off3 + h3]);
+#pragma unroll
+                    for (int h3 = 0; h3 < kMaxLayerHits; ++h3)
+                        if (h3 < n3) S.XT[t + h3] = pack16(x2, y3[h3]);
                 }
-                for (int32_t h4 = 0; h4 < n4; ++h4) S.XT[b4 + h4] = pack16(S.G[off4 + h4], 1);
+#pragma unroll
+                for (int h4 = 0; h4 < kMaxLayerHits; ++h4)
+                    if (h4 < n4) S.XT[b4 + h4] = pack16(y4[h4], 1);
             }
             // groups whose first combination inside [cs, ce) belongs to this road
             const int32_t glo = rb <= cs ? g_lo : (rb + 3) >> 2;
