@@ -59,7 +59,7 @@ UnpackWs carve_unpack(Carver &c, int64_t n_words) {
 }
 
 struct BatchWs {
-    uint32_t *tickets;  // [0] fused-kernel tiles (or events), [1] pre-pass blocks
+    uint32_t *tickets;  // [0] fused-kernel tiles (or events of the event schedule); rest spare
     int64_t *n_events;  // events of the batch
     int32_t *efr;       // first road of every event
     int64_t events_cap;
