@@ -114,3 +114,24 @@ def test_gather_results_matches_the_batch_outputs(bank, where):
         assert np.array_equal(roads["event"], to_np(out["road_event"]))
         assert np.array_equal(roads["set"], to_np(out["road_set"]))
     L.svt_release_graphs()
+
+
+def test_gather_results_reports_the_kept_count(bank):
+    """With a kept list the header's fourth word is the accepted count (the oracle's)."""
+    cfg = oracle.make_config()
+    dbank = P.device_bank(bank.f, bank.q)
+    s = synth.make_sample("c4", n_events=12, bank=bank)
+    ref = oracle.run(s.words, bank.f, bank.q, cfg)
+    nr, nc = ref["n_roads"], ref["n_combos"]
+    r = P.BatchRunner(gpu_cfg(cfg), dbank, len(s.words), nr, nc, kept_cap=nc, graph=False,
+                      with_c=False)
+    r.load(P.words_tensor(s.words)).run()
+    buf = torch.zeros(L.GATHER_HEADER_BYTES + L.GATHER_BYTES_PER_ROAD * nr, dtype=torch.uint8,
+                      device="cuda")
+    L.PreparedGather(r.roads, r.best, r.road_cap, r.d_n[0:1], r.d_n[1:2], r.d_n[2:3], r.d_n[3:4],
+                     r.d_err, buf, nr)(r.stream)
+    r.stream.synchronize()
+    head, roads = L.gathered(buf.cpu().numpy())
+    assert head["n_kept"] == int(ref["n_kept"]) > 0
+    assert (head["n_roads"], head["n_combos"]) == (nr, nc)
+    assert roads is not None and len(roads["k"]) == nr
