@@ -281,15 +281,25 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
     const int nown = nloc < kPB ? nloc : kPB;
     const int j0 = tid * kPW;
     const bool aligned16 = (reinterpret_cast<uintptr_t>(a.words) & 15) == 0;
+    uint32_t wv[kPW];  // this thread's words, kept for the flags below
     if (aligned16 && j0 + kPW <= nown) {
         const uint4 *p = reinterpret_cast<const uint4 *>(a.words + base + j0);
         uint4 *q = reinterpret_cast<uint4 *>(sw + kOff + j0);
 #pragma unroll
-        for (int v = 0; v < kPW / 4; ++v) q[v] = p[v];
+        for (int v = 0; v < kPW / 4; ++v) {
+            const uint4 u = p[v];
+            q[v] = u;
+            wv[4 * v] = u.x;
+            wv[4 * v + 1] = u.y;
+            wv[4 * v + 2] = u.z;
+            wv[4 * v + 3] = u.w;
+        }
     } else {
 #pragma unroll
-        for (int e = 0; e < kPW; ++e)
-            sw[kOff + j0 + e] = (j0 + e < nloc) ? a.words[base + j0 + e] : 0u;
+        for (int e = 0; e < kPW; ++e) {
+            wv[e] = (j0 + e < nloc) ? a.words[base + j0 + e] : 0u;
+            sw[kOff + j0 + e] = wv[e];
+        }
     }
     if (tid < kTail) sw[kOff + kPB + tid] = (kPB + tid < nloc) ? a.words[base + kPB + tid] : 0u;
     if (tid == 0) sw[kOff - 1] = base > 0 ? a.words[base - 1] : 0u;
@@ -303,8 +313,8 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
     for (int e = 0; e < kPW; ++e) {
         const int j = j0 + e;
         if (j < nown) {
-            const uint32_t x = sw[kOff + j];
-            const uint32_t px = sw[kOff + j - 1];
+            const uint32_t x = wv[e];
+            const uint32_t px = e == 0 ? sw[kOff + j - 1] : wv[e - 1];
             const bool first = (base + j == 0);
             const bool r = first || w_tags(x) != w_tags(px);
             const bool v = first || w_etag(x) != w_etag(px);
