@@ -573,50 +573,46 @@ __device__ __forceinline__ void fit_group(const FArgs &a, const Stage &S, int ri
     store_group<REC>(a, gi, slots, acc_bits, vp0, vp1, vp2, vc0, vc1, vc2, vchi);
 }
 
-// A group that spans road boundaries: each slot is fitted with the constants of its own road
-// (road ri holds the first valid slot; later roads follow in staging order) and written on its
-// own.  Rare (at most one group per road), so it is kept small rather than fast.
+// One combination ci (relative to the tile start) of a group that spans a road boundary, fitted
+// with the constants of its own road (the group's first road is r; later roads follow in
+// staging order) and written on its own.  Such groups are few (at most one per road), but at
+// small roads one chunk can hold hundreds of them; one lane per combination rather than per
+// group spreads them over four times as many lanes.
 template <bool FOLD, int REC>
-__device__ void fit_group_split(const FArgs &a, const Stage &S, int ri, int32_t rel0,
-                                uint32_t slots, int64_t tile_start, int64_t r_first) {
+__device__ void fit_slot(const FArgs &a, const Stage &S, int r, int32_t ci, int64_t tile_start,
+                         int64_t r_first) {
     const int nr = S.nr;
-    const int64_t gi = tile_start + rel0;
-    unsigned long long *keys = reinterpret_cast<unsigned long long *>(a.best.chi2);
-    int r = ri;
-#pragma unroll 1
-    for (int e = 0; e < 4; ++e) {
-        if (!((slots >> e) & 1u)) continue;
-        const int32_t ci = rel0 + e;
-        while (r + 1 < nr && ci >= S.rb[r] + S.meta[r].C()) ++r;  // skips empty roads
-        const int32_t k = ci - S.rb[r];
-        const Fit f = fit_combo<FOLD>(S.meta[r], S.rc[r], static_cast<uint32_t>(k), S.XT, a.shift);
-        const bool acc = f.chi2 <= a.cut;
-        if (REC != kRecNone) {
-            a.rec.p0[gi + e] = f.v[0];
-            a.rec.p1[gi + e] = f.v[1];
-            a.rec.p2[gi + e] = f.v[2];
-            a.rec.chi2[gi + e] = f.chi2;
-        }
-        if (REC == kRecRows) {
-            if (a.rec.c0) a.rec.c0[gi + e] = f.v[3];
-            if (a.rec.c1) a.rec.c1[gi + e] = f.v[4];
-            if (a.rec.c2) a.rec.c2[gi + e] = f.v[5];
-        }
-        a.accept[gi + e] = acc ? 1 : 0;
-        if (acc) {
-            if (a.kb_counts) atomicAdd(a.kb_counts + (gi + e) / kKeptBlock, 1ull);
-            atomicMin(keys + r_first + r,
-                      static_cast<unsigned long long>(best_key(f.chi2, static_cast<uint32_t>(k))));
-            atomicAdd(a.best.n_accept + r_first + r, 1);
-        }
+    while (r + 1 < nr && ci >= S.rb[r] + S.meta[r].C()) ++r;  // skips empty roads
+    const int32_t k = ci - S.rb[r];
+    const Fit f = fit_combo<FOLD>(S.meta[r], S.rc[r], static_cast<uint32_t>(k), S.XT, a.shift);
+    const bool acc = f.chi2 <= a.cut;
+    const int64_t gi = tile_start + ci;
+    if (REC != kRecNone) {
+        a.rec.p0[gi] = f.v[0];
+        a.rec.p1[gi] = f.v[1];
+        a.rec.p2[gi] = f.v[2];
+        a.rec.chi2[gi] = f.chi2;
+    }
+    if (REC == kRecRows) {
+        if (a.rec.c0) a.rec.c0[gi] = f.v[3];
+        if (a.rec.c1) a.rec.c1[gi] = f.v[4];
+        if (a.rec.c2) a.rec.c2[gi] = f.v[5];
+    }
+    a.accept[gi] = acc ? 1 : 0;
+    if (acc) {
+        unsigned long long *keys = reinterpret_cast<unsigned long long *>(a.best.chi2);
+        if (a.kb_counts) atomicAdd(a.kb_counts + gi / kKeptBlock, 1ull);
+        atomicMin(keys + r_first + r,
+                  static_cast<unsigned long long>(best_key(f.chi2, static_cast<uint32_t>(k))));
+        atomicAdd(a.best.n_accept + r_first + r, 1);
     }
 }
 
 // Compute waves, for batches of small roads: fit every combination of a staged chunk that lies
 // inside its tile.  A lane takes a group of 4 consecutive combinations.  Groups inside one
 // road take the uniform path (one road's constants, full 16-byte stores); the few groups that
-// span a road boundary are listed by the loader and fitted first, each slot with its own road,
-// so that every group is written by exactly one lane.  Fitting the listed groups first lets the
+// span a road boundary are listed by the loader and fitted first, one combination per lane with
+// its own road, so that every combination is written by exactly one lane.  Fitting the listed groups first lets the
 // main pass complete their cache lines while the lines are still in L2 (the other order
 // leaves 16-byte holes that are filled too late and reach HBM twice: 1.37x the algorithmic
 // writes at c2 against 1.18x).
@@ -627,18 +623,14 @@ __device__ void consume_listed(const FArgs &a, Stage &S) {
     const int32_t ng = g_hi - g_lo;
     const int lane = lane_id();
     const int32_t nx = S.nx;
-    while (true) {
+    while (true) {  // the listed groups, one combination per lane
         const int32_t base = claim64(&S.work[1]);
-        if (base >= nx) break;
+        if (base >= 4 * nx) break;
         const int32_t j = base + lane;
-        if (j < nx) {
-            const int32_t off = S.X[j];
-            const int32_t rel0 = (g_lo + off) << 2;
-            uint32_t valid = 0;
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                valid |= (rel0 + e >= cs && rel0 + e < ce) ? (1u << e) : 0u;
-            fit_group_split<FOLD, REC>(a, S, S.M[off], rel0, valid, tile_start, r_first);
+        if (j < 4 * nx) {
+            const int32_t off = S.X[j >> 2];
+            const int32_t ci = ((g_lo + off) << 2) + (j & 3);
+            if (ci >= cs && ci < ce) fit_slot<FOLD, REC>(a, S, S.M[off], ci, tile_start, r_first);
         }
     }
     while (true) {
