@@ -820,7 +820,14 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG == 256 ? 
     __syncthreads();
     int cur = 0;
     while (!S[cur].done) {
-        if (wave == 0) produce(a, S[cur ^ 1], L, n_roads, n_combos, n_tiles, T, qlmask);
+        // The loader runs at raised issue priority while it stages: its chain of dependent
+        // loads and LDS writes sets the pace of the pipeline, and on its SIMD it would otherwise
+        // wait for issue slots behind the compute waves' arithmetic (about 2 % at c2 and c5).
+        if (wave == 0) {
+            __builtin_amdgcn_s_setprio(3);
+            produce(a, S[cur ^ 1], L, n_roads, n_combos, n_tiles, T, qlmask);
+            __builtin_amdgcn_s_setprio(0);
+        }
         // every wave, the loader once it has staged the next chunk
         if (listed)
             consume_listed<FOLD, REC>(a, S[cur]);
