@@ -58,7 +58,18 @@ struct FArgs {
     int64_t combo_cap;
     int32_t records;        // 0: kept-only mode, no per-combination records
     int32_t fold;           // shift <= 15: ql packed with f_j4 (see fit_xyz)
+    int32_t num_cus;        // CUs of the device (the grid holds wgs_per_cu workgroups per CU)
 };
+
+// Wave issue priority from a run-time level 0..2 (the instruction takes an immediate).
+__device__ __forceinline__ void set_prio(int p) {
+    if (p <= 0)
+        __builtin_amdgcn_s_setprio(0);
+    else if (p == 1)
+        __builtin_amdgcn_s_setprio(1);
+    else
+        __builtin_amdgcn_s_setprio(2);
+}
 
 // Per-road indexing data of the current chunk, in LDS, packed into 16 bytes so that the reads
 // of the roads one wave works on fall in different banks.  Field widths: n4 <= 8 and
@@ -819,15 +830,23 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG == 256 ? 
     }
     __syncthreads();
     int cur = 0;
+    // Workgroups sharing a CU: equal priorities issue oldest first, and the dispatcher hands
+    // out blocks 0 .. num_cus - 1 one per CU before the next num_cus, so the last-dispatched
+    // workgroup of a CU (slot = blockIdx.x / num_cus) fitted its chunks about 20 % slower and
+    // ended 4-5 us after the first at c2; the kernel waits for it.  The compute priority rotates
+    // over the slots from chunk to chunk (youngest highest first), so the workgroups of a CU
+    // take turns; all waves of a workgroup share one level.
+    const int slot = static_cast<int>(blockIdx.x) / (a.num_cus > 0 ? a.num_cus : 1);
+    int iter = 0;
     while (!S[cur].done) {
-        // The loader runs at raised issue priority while it stages: its chain of dependent
-        // loads and LDS writes sets the pace of the pipeline, and on its SIMD it would otherwise
-        // wait for issue slots behind the compute waves' arithmetic (about 2 % at c2 and c5).
+        // The loader runs at the top priority while it stages: its chain of dependent loads
+        // and LDS writes sets the pace of the pipeline, and on its SIMD it would otherwise wait
+        // for issue slots behind the compute waves' arithmetic (about 2 % at c2 and c5).
         if (wave == 0) {
             __builtin_amdgcn_s_setprio(3);
             produce(a, S[cur ^ 1], L, n_roads, n_combos, n_tiles, T, qlmask);
-            __builtin_amdgcn_s_setprio(0);
         }
+        set_prio((slot + iter) % 3);
         // every wave, the loader once it has staged the next chunk
         if (listed)
             consume_listed<FOLD, REC>(a, S[cur]);
@@ -835,6 +854,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG == 256 ? 
             consume_inline<FOLD, REC>(a, S[cur]);
         __syncthreads();
         cur ^= 1;
+        ++iter;
     }
 }
 
@@ -861,6 +881,7 @@ FArgs make_args(const FusedLaunch &f) {
     a.combo_cap = f.combo_cap;
     a.records = f.kept_only ? 0 : 1;
     a.fold = f.cfg.shift <= 15 ? 1 : 0;
+    a.num_cus = f.num_cus;
     return a;
 }
 
