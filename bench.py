@@ -417,6 +417,42 @@ def main():
                     kernel="k_fused", kernel_ms=round(k_ms, 5), algorithmic_bytes=alg,
                     bytes_per_combination=round(alg / n_combos, 3))
 
+    # ---- several batches in flight: more runners, each with its own stream and graph -------
+    # (not the headline: `value` is one pass at a time.  With independent batches queued on
+    # several streams, one batch's latency-bound pre-pass and kernel tails can overlap another's
+    # fused kernel; this is the serving slots' situation at a high arrival rate.)
+    in_flight = None
+    if not args.no_kept_only:
+        in_flight = {}
+        for n_fl in (2, 3):
+            log(f"{n_fl} batches in flight")
+            extra = []
+            for _ in range(n_fl - 1):
+                r = P.BatchRunner(gcfg, dbank, n_words, n_roads, n_combos, kept_cap=0, tune=tune,
+                                  graph=not args.no_graph, with_c=False)
+                r.load(words)
+                extra.append(r)
+            group = [runner] + extra
+            for _ in range(W):
+                for r in group:
+                    r.run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(K):
+                for r in group:
+                    r.run()
+            torch.cuda.synchronize()
+            fl_s = (time.perf_counter() - t0) / K
+            assert all(r.error()[0] == 0 for r in group), [r.error() for r in group]
+            same = all(torch.equal(runner.result()[k], r.result()[k]) for r in extra
+                       for k in ("best_k", "best_chi2", "best_p0", "best_n_accept"))
+            in_flight[str(n_fl)] = dict(value=n_fl * n_combos / fl_s,
+                                        ms_per_batch=round(fl_s / n_fl * 1e3, 5),
+                                        over_one_at_a_time=round(batch_s / (fl_s / n_fl), 3),
+                                        same_results=same)
+            L.svt_release_graphs()  # (before the buffers the graphs refer to go away)
+            del extra, group
+
     # ---- ablation: one event per workgroup instead of flat combination tiles ---------------
     events_schedule = None
     if not args.no_kept_only:
@@ -519,6 +555,7 @@ def main():
                     device=dev_name),
         roofline=roofline, cpu_baseline=cpu, kept_only=kept_only,
         event_per_workgroup=events_schedule, plain=plain,
+        batches_in_flight=in_flight,
         uneven_autotuned=uneven,
         serving=serving, transfer=transfer, max_scale=large)
     print(json.dumps(out), flush=True)
