@@ -81,6 +81,23 @@ def test_batch_repeats_are_deterministic(samples, bank):
     L.svt_release_graphs()
 
 
+def test_batches_in_flight_on_two_streams(samples, bank):
+    """Two runners, each with its own stream and captured graph, replayed back to back with no
+    synchronisation between them (their kernels overlap on the device): each batch still gives
+    the oracle's bytes, on every replay."""
+    (s2, ref2), (s3, ref3) = samples["c2"], samples["c3"]
+    _, r2 = run_batch(s2.words, bank.f, bank.q, CFG, ref=ref2, graph=True)
+    _, r3 = run_batch(s3.words, bank.f, bank.q, CFG, ref=ref3, graph=True)
+    for rep in range(3):
+        for _ in range(4):
+            r2.run()
+            r3.run()
+        torch.cuda.synchronize()
+        compare(ref2, r2.result(), BATCH_KEYS, f"c2 in flight, round {rep}")
+        compare(ref3, r3.result(), BATCH_KEYS, f"c3 in flight, round {rep}")
+    L.svt_release_graphs()
+
+
 @pytest.mark.parametrize("seed", range(12))
 def test_tiny_random_streams(bank, seed):
     """Ragged tiny inputs: zero-combination roads, extreme constants and coordinates, cuts."""
