@@ -622,11 +622,11 @@ __device__ void fit_slot(const FArgs &a, const Stage &S, int r, int32_t ci, int6
 // Compute waves, for batches of small roads: fit every combination of a staged chunk that lies
 // inside its tile.  A lane takes a group of 4 consecutive combinations.  Groups inside one
 // road take the uniform path (one road's constants, full 16-byte stores); the few groups that
-// span a road boundary are listed by the loader and fitted first, one combination per lane with
-// its own road, so that every combination is written by exactly one lane.  Fitting the listed groups first lets the
-// main pass complete their cache lines while the lines are still in L2 (the other order
-// leaves 16-byte holes that are filled too late and reach HBM twice: 1.37x the algorithmic
-// writes at c2 against 1.18x).
+// span a road boundary are listed by the loader and fitted first, one combination per lane
+// with its own road's constants, so that every combination is written by exactly one lane.
+// Fitting the listed groups first lets the main pass complete their cache lines while the
+// lines are still in L2 (the other order leaves 16-byte holes that are filled too late and
+// reach HBM twice: 1.37x the algorithmic writes at c2 against 1.18x when it was measured).
 template <bool FOLD, int REC>
 __device__ void consume_listed(const FArgs &a, Stage &S) {
     const int32_t cs = S.cs, ce = S.ce, g_lo = S.g_lo, g_hi = S.g_hi;
