@@ -18,6 +18,7 @@ pytestmark = pytest.mark.gpu
 
 CFG = oracle.make_config(chi2_cut=synth.DEFAULT_CHI2_CUT)
 TUNES = [L.make_tune(4096, 64, 256, 2), L.make_tune(8192, 64, 256, 3),
+         L.make_tune(4096, 64, 256, 4),  # a fourth workgroup per CU: a fourth priority slot
          L.make_tune(4096, 64, 512, 1), L.make_tune(8192, 64, 512, 2),
          L.make_tune(4096, 64, 256, 4, 1)]  # the last: one event per workgroup
 
