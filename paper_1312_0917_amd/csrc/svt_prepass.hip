@@ -37,7 +37,8 @@ constexpr int kPT = 256;                  // threads per block
 constexpr int kPB = kPrepassBlockWords;   // 2048 words per block
 constexpr int kPW = kPB / kPT;            // 8 words per thread
 constexpr int kTail = 64;                 // words staged past the block's own
-constexpr int kOff = 4;                   // sw[kOff - 1] = word before the block (16-byte aligned body)
+constexpr int kOff = 4;                   // sw[kOff - 1] = word before the block; the body
+                                          // starts 16-byte aligned
 constexpr uint64_t kStAgg = 1ull << 62;
 constexpr uint64_t kStIncl = 2ull << 62;
 constexpr uint64_t kStMask = 3ull << 62;
@@ -244,10 +245,9 @@ __device__ void look_back2(const PArgs &a, int64_t n, int64_t b, uint64_t agg0, 
     }
 }
 
-
 // Per owned road, in LDS: s_road[rl] = first local word (12 bits) | events started in the block
-// up to that word (12 bits) << 12 | the word starts an event << 24; s_info[rl] = hits per layer (4 bits each) | too-many-hits
-// << 20 | no-constant-set << 21.
+// up to that word (12 bits) << 12 | the word starts an event << 24; s_info[rl] = hits per layer
+// (4 bits each) | too-many-hits << 20 | no-constant-set << 21.
 constexpr uint32_t kInfoOver = 1u << 20;
 constexpr uint32_t kInfoSet = 1u << 21;
 

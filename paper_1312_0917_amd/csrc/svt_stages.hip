@@ -25,7 +25,8 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_count(const uint32_t *__res
     const int64_t nb = (n + kSegBlockWords - 1) / kSegBlockWords;
     const bool aligned = (reinterpret_cast<uintptr_t>(words) & 15) == 0;
     for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-        const int64_t base = b * kSegBlockWords + static_cast<int64_t>(threadIdx.x) * kSegWordsPerThread;
+        const int64_t base =
+            b * kSegBlockWords + static_cast<int64_t>(threadIdx.x) * kSegWordsPerThread;
         uint32_t w[kSegWordsPerThread];
         if (aligned && base + kSegWordsPerThread <= n) {
             const uint4 *p = reinterpret_cast<const uint4 *>(words + base);
@@ -36,7 +37,8 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_count(const uint32_t *__res
             }
         } else {
 #pragma unroll
-            for (int e = 0; e < kSegWordsPerThread; ++e) w[e] = (base + e < n) ? words[base + e] : 0u;
+            for (int e = 0; e < kSegWordsPerThread; ++e)
+                w[e] = (base + e < n) ? words[base + e] : 0u;
         }
         uint32_t prev = (base > 0 && base <= n) ? words[base - 1] : 0u;
         int64_t nr = 0, ne = 0;
@@ -119,7 +121,8 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_emit(const uint32_t *__rest
     const int64_t n = load_size(n_words_s);
     const int64_t nb = (n + kSegBlockWords - 1) / kSegBlockWords;
     for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-        const int64_t base = b * kSegBlockWords + static_cast<int64_t>(threadIdx.x) * kSegWordsPerThread;
+        const int64_t base =
+            b * kSegBlockWords + static_cast<int64_t>(threadIdx.x) * kSegWordsPerThread;
         uint32_t w[kSegWordsPerThread];
 #pragma unroll
         for (int e = 0; e < kSegWordsPerThread; ++e) w[e] = (base + e < n) ? words[base + e] : 0u;
