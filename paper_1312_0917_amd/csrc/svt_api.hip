@@ -376,9 +376,10 @@ static svt_status batch_sequence(const FusedLaunch &f, const BatchWs &w, int64_t
     p.event_cap = w.events_cap;
     p.d_n_events = w.n_events;
     uint64_t *err = f.err;
-    SVT_TRY(launch_batch_reset(p, d_n_kept, stream));
+    // (the kept-list block counts are cleared with the rest: the fused kernel adds to them)
+    SVT_TRY(launch_batch_reset(p, d_n_kept, d_n_kept ? w.kb : nullptr, d_n_kept ? w.kbn : 0,
+                               stream));
     SVT_TRY(launch_prepass(p, stream));
-    if (d_n_kept) SVT_TRY(launch_zero(w.kb, w.kbn, stream));
     if (timing) SVT_TRY(hipEventRecord(g_ev_start, stream));
     if (f.tune.schedule == 1)
         SVT_TRY(launch_fit_events(f, w.efr, w.n_events, w.events_cap, stream));

@@ -210,7 +210,6 @@ hipError_t launch_fused(const FusedLaunch &f, hipStream_t s);
 // kernel, for the ablation against flat combination tiles.
 hipError_t launch_fit_events(const FusedLaunch &f, const int32_t *event_first_road,
                              const int64_t *d_n_events, int64_t event_cap, hipStream_t s);
-hipError_t launch_zero(int64_t *p, int64_t n, hipStream_t s);
 // Per road: turn the best-track key left in best.chi2 into (k, chi2, p0..p2), reading the
 // parameters from the records, or fitting them again from the grouped coordinates when bank
 // and coords are given (exact rescan of the records for a road whose key saturated).
@@ -243,8 +242,10 @@ struct PrepassLaunch {
     int64_t event_cap;
     int64_t *d_n_events;
 };
-// Clears the error word, both tickets, *d_n_kept (nullable) and the status words in use.
-hipError_t launch_batch_reset(const PrepassLaunch &p, int64_t *d_n_kept, hipStream_t s);
+// Clears the error word, both tickets, *d_n_kept (nullable), the status words in use and
+// zero[0 .. n_zero) (the kept-list block counts; nullable).
+hipError_t launch_batch_reset(const PrepassLaunch &p, int64_t *d_n_kept, int64_t *zero,
+                              int64_t n_zero, hipStream_t s);
 hipError_t launch_prepass(const PrepassLaunch &p, hipStream_t s);
 
 }  // namespace svt

@@ -904,10 +904,6 @@ hipError_t launch_fused_t(const FArgs &a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-__global__ void k_zero(int64_t *p, int64_t n) {
-    for (int64_t i = gtid(); i < n; i += gstride()) p[i] = 0;
-}
-
 }  // namespace
 
 bool fused_tune_supported(const svt_tune &t) {
@@ -926,14 +922,6 @@ hipError_t launch_fused(const FusedLaunch &f, hipStream_t s) {
     if (f.tune.wg_size == 256) return launch_fused_t<256>(a, grid, s);
     if (f.tune.wg_size == 512) return launch_fused_t<512>(a, grid, s);
     return hipErrorInvalidValue;
-}
-
-hipError_t launch_zero(int64_t *p, int64_t n, hipStream_t s) {
-    int64_t blocks = (n + 255) / 256;
-    if (blocks < 1) blocks = 1;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, p, n);
-    return hipGetLastError();
 }
 
 }  // namespace svt

@@ -493,10 +493,11 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
 }
 
 // Clears the error word, the work tickets (the fused kernel's tile counter is the first), the
-// kept count and the look-back status words
-// of the blocks this pass will use.
+// kept count, the look-back status words of the blocks this pass will use and, when given,
+// zero[0 .. n_zero) (the kept list's per-block counts, which the fused kernel adds to).
 __global__ void k_batch_reset(uint64_t *err, uint32_t *tickets, int64_t *d_n_kept,
-                              int64_t *status, int64_t nb_cap, Sizes nw) {
+                              int64_t *status, int64_t nb_cap, Sizes nw, int64_t *zero,
+                              int64_t n_zero) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *err = SVT_NO_ERROR;
         tickets[0] = 0;
@@ -510,6 +511,8 @@ __global__ void k_batch_reset(uint64_t *err, uint32_t *tickets, int64_t *d_n_kep
         status[i] = 0;
         status[nb_cap + i] = 0;
     }
+    if (zero)
+        for (int64_t i = gtid(); i < n_zero; i += gstride()) zero[i] = 0;
 }
 
 }  // namespace
@@ -543,12 +546,15 @@ hipError_t launch_prepass(const PrepassLaunch &p, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch_reset(const PrepassLaunch &p, int64_t *d_n_kept, hipStream_t s) {
-    int64_t blocks = (p.nb_cap + 255) / 256;
+hipError_t launch_batch_reset(const PrepassLaunch &p, int64_t *d_n_kept, int64_t *zero,
+                              int64_t n_zero, hipStream_t s) {
+    const int64_t items = zero && n_zero > p.nb_cap ? n_zero : p.nb_cap;
+    int64_t blocks = (items + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(k_batch_reset, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
-                       p.err, p.tickets, d_n_kept, p.status, p.nb_cap, p.nw);
+                       p.err, p.tickets, d_n_kept, p.status, p.nb_cap, p.nw, zero,
+                       zero ? n_zero : 0);
     return hipGetLastError();
 }
 
