@@ -386,12 +386,20 @@ static svt_status batch_sequence(const FusedLaunch &f, const BatchWs &w, int64_t
     else
         SVT_TRY(launch_fused(f, stream));
     if (timing) SVT_TRY(hipEventRecord(g_ev_stop, stream));
+    // the kept list's block counts are scanned by one extra workgroup of the finalize launch
+    ScanJob job;
+    if (d_n_kept) {
+        job.data = w.kb;
+        job.n = nc;
+        job.div = kKeptBlock;
+        job.tot = d_n_kept;
+        job.cap = kept ? kept_cap : -1;
+        job.cap_index = 2;
+    }
     SVT_TRY(launch_best_finalize(f.roads, nr, f.kept_only ? svt_fitrec{} : f.rec, nc, f.best,
-                                 f.cfg.chi2_cut, err, true, f.bank, f.coords, f.cfg.shift,
+                                 f.cfg.chi2_cut, err, true, f.bank, f.coords, f.cfg.shift, job,
                                  stream));
     if (d_n_kept) {
-        SVT_TRY(launch_scan(w.kb, 0, 1, nc, kKeptBlock, d_n_kept, nullptr, kept ? kept_cap : -1,
-                            2, err, true, stream));
         if (kept && f.kept_only)
             SVT_TRY(launch_kept_refit(f.accept, nc, nr, w.kbn, w.kb, f.roads, w.tfr,
                                       f.tune.tile_combos, f.bank, f.coords, f.cfg.shift, kept,

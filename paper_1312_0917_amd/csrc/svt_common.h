@@ -213,10 +213,22 @@ hipError_t launch_fit_events(const FusedLaunch &f, const int32_t *event_first_ro
 // Per road: turn the best-track key left in best.chi2 into (k, chi2, p0..p2), reading the
 // parameters from the records, or fitting them again from the grouped coordinates when bank
 // and coords are given (exact rescan of the records for a road whose key saturated).
+// An in-place exclusive scan of ceil(n / div) counts with its total written to *tot and checked
+// against cap (class CAPACITY, index cap_index) when cap >= 0; data == nullptr: no job.
+struct ScanJob {
+    int64_t *data = nullptr;
+    Sizes n{};
+    int64_t div = 1;
+    int64_t *tot = nullptr;
+    int64_t cap = -1;
+    uint32_t cap_index = 0;
+};
+// Best track per road from the keys; with a scan job, one extra workgroup does that scan.
 hipError_t launch_best_finalize(const svt_roads &roads, Sizes n_roads, const svt_fitrec &rec,
                                 Sizes n_combos, const svt_best &best, int64_t cut,
                                 uint64_t *err, bool skip_if_error, const svt_fconst *bank,
-                                const int16_t *coords, int32_t shift, hipStream_t s);
+                                const int16_t *coords, int32_t shift, const ScanJob &job,
+                                hipStream_t s);
 bool fused_tune_supported(const svt_tune &t);
 
 // Single-pass unpack + combine of the batched path (decoupled look-back over word blocks).

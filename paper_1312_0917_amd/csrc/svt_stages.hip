@@ -65,25 +65,14 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_count(const uint32_t *__res
     }
 }
 
-// ---- single-workgroup in-place exclusive scan, one workgroup per column ------------------
-__global__ __launch_bounds__(kScanThreads) void k_scan(int64_t *data, int64_t col_stride,
-                                                       Sizes n_s, int64_t div, int64_t *tot0,
-                                                       int64_t *tot1, int64_t cap0,
-                                                       uint32_t cap_index, uint64_t *err,
-                                                       int32_t skip_if_error) {
-    __shared__ int64_t tmp[kScanThreads / kWaveSize + 1];
+// ---- single-workgroup in-place exclusive scan ---------------------------------------------
+// Exclusive scan of col[0 .. n) in place by one workgroup of NT threads; the total goes to *tot
+// (nullable).  tmp holds NT / 64 + 1 values.
+template <int NT>
+__device__ int64_t scan_column(int64_t *col, int64_t n, int64_t *tot, int64_t *tmp) {
     constexpr int kItems = 4;
-    if (skip_if_error && has_error(err)) {
-        if (threadIdx.x == 0) {
-            int64_t *tot = blockIdx.x == 0 ? tot0 : tot1;
-            if (tot) *tot = -1;
-        }
-        return;
-    }
-    const int64_t n = (load_size(n_s) + div - 1) / div;
-    int64_t *col = data + blockIdx.x * col_stride;
     int64_t carry = 0;
-    for (int64_t base = 0; base < n; base += static_cast<int64_t>(kScanThreads) * kItems) {
+    for (int64_t base = 0; base < n; base += static_cast<int64_t>(NT) * kItems) {
         const int64_t i0 = base + static_cast<int64_t>(threadIdx.x) * kItems;
         int64_t v[kItems];
         int64_t s = 0;
@@ -93,7 +82,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int64_t *data, int64_t co
             s += v[e];
         }
         int64_t total;
-        int64_t ex = block_excl_scan<int64_t, kScanThreads>(s, tmp, total);
+        int64_t ex = block_excl_scan<int64_t, NT>(s, tmp, total);
         int64_t run = carry + ex;
 #pragma unroll
         for (int e = 0; e < kItems; ++e) {
@@ -102,12 +91,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int64_t *data, int64_t co
         }
         carry += total;
     }
-    if (threadIdx.x == 0) {
-        int64_t *tot = blockIdx.x == 0 ? tot0 : tot1;
-        if (tot) *tot = carry;
-        if (blockIdx.x == 0 && cap0 >= 0 && carry > cap0)
-            report(err, SVT_ERRCLASS_CAPACITY, cap_index);
+    if (threadIdx.x == 0 && tot) *tot = carry;
+    return carry;
+}
+
+// One workgroup per column; column 0's total is checked against cap0 (class CAPACITY, index
+// cap_index) when cap0 >= 0.
+__global__ __launch_bounds__(kScanThreads) void k_scan(int64_t *data, int64_t col_stride,
+                                                       Sizes n_s, int64_t div, int64_t *tot0,
+                                                       int64_t *tot1, int64_t cap0,
+                                                       uint32_t cap_index, uint64_t *err,
+                                                       int32_t skip_if_error) {
+    __shared__ int64_t tmp[kScanThreads / kWaveSize + 1];
+    int64_t *tot = blockIdx.x == 0 ? tot0 : tot1;
+    if (skip_if_error && has_error(err)) {
+        if (threadIdx.x == 0 && tot) *tot = -1;
+        return;
     }
+    const int64_t n = (load_size(n_s) + div - 1) / div;
+    const int64_t carry = scan_column<kScanThreads>(data + blockIdx.x * col_stride, n, tot, tmp);
+    if (threadIdx.x == 0 && blockIdx.x == 0 && cap0 >= 0 && carry > cap0)
+        report(err, SVT_ERRCLASS_CAPACITY, cap_index);
 }
 
 // ---- unpack 2: write each road's first word, tag and event ordinal -----------------------
@@ -453,14 +457,33 @@ __device__ inline int64_t refit_combo(const svt_fconst *__restrict__ bank,
 // With bank and coords (batched path), the best track's parameters are fitted again from its
 // hits instead of gathered from the three record arrays: one coordinate line per road instead
 // of three scattered reads.
-__global__ void k_best_finalize(svt_roads roads, Sizes n_roads_s, svt_fitrec rec,
-                                Sizes n_combos_s, svt_best best, int64_t cut, uint64_t *err,
-                                int32_t skip_if_error, const svt_fconst *bank,
-                                const int16_t *coords, int32_t shift) {
+// With a scan job (job.data non-null), the grid's last block does that scan instead of roads:
+// the kept list's per-block counts, in the same launch (it reads nothing the roads write).
+__global__ __launch_bounds__(256) void k_best_finalize(svt_roads roads, Sizes n_roads_s,
+                                                       svt_fitrec rec, Sizes n_combos_s,
+                                                       svt_best best, int64_t cut, uint64_t *err,
+                                                       int32_t skip_if_error,
+                                                       const svt_fconst *bank,
+                                                       const int16_t *coords, int32_t shift,
+                                                       ScanJob job) {
+    const int64_t road_blocks = job.data ? gridDim.x - 1 : gridDim.x;
+    if (job.data && blockIdx.x == road_blocks) {
+        __shared__ int64_t tmp[256 / kWaveSize + 1];
+        if (skip_if_error && has_error(err)) {
+            if (threadIdx.x == 0 && job.tot) *job.tot = -1;
+            return;
+        }
+        const int64_t n = (load_size(job.n) + job.div - 1) / job.div;
+        const int64_t carry = scan_column<256>(job.data, n, job.tot, tmp);
+        if (threadIdx.x == 0 && job.cap >= 0 && carry > job.cap)
+            report(err, SVT_ERRCLASS_CAPACITY, job.cap_index);
+        return;
+    }
     if (skip_if_error && has_error(err)) return;
     const int64_t n_roads = load_size(n_roads_s);
     const int64_t n_combos = load_size(n_combos_s);
-    for (int64_t r = gtid(); r < n_roads; r += gstride()) {
+    const int64_t stride = road_blocks * blockDim.x;
+    for (int64_t r = gtid(); r < n_roads; r += stride) {
         uint64_t key = reinterpret_cast<uint64_t *>(best.chi2)[r];
         const int64_t cb = roads.combo_begin[r];
         const int64_t nc = roads.ncombo[r];
@@ -800,17 +823,19 @@ hipError_t launch_select(const svt_config &cfg, const svt_roads &roads, int64_t 
     if (n_roads > 0)
         return launch_best_finalize(roads, Sizes{n_roads, nullptr, n_roads}, rec,
                                     Sizes{n_combos, nullptr, n_combos}, best, cfg.chi2_cut, err,
-                                    false, nullptr, nullptr, 0, s);
+                                    false, nullptr, nullptr, 0, ScanJob{}, s);
     return hipGetLastError();
 }
 
 hipError_t launch_best_finalize(const svt_roads &roads, Sizes n_roads, const svt_fitrec &rec,
                                 Sizes n_combos, const svt_best &best, int64_t cut,
                                 uint64_t *err, bool skip_if_error, const svt_fconst *bank,
-                                const int16_t *coords, int32_t shift, hipStream_t s) {
-    const int64_t g = clamp_grid((n_roads.cap + 255) / 256, 1 << 14);
+                                const int16_t *coords, int32_t shift, const ScanJob &job,
+                                hipStream_t s) {
+    const int64_t g = clamp_grid((n_roads.cap + 255) / 256, 1 << 14) + (job.data ? 1 : 0);
     hipLaunchKernelGGL(k_best_finalize, dim3(g), dim3(256), 0, s, roads, n_roads, rec, n_combos,
-                       best, cut, err, static_cast<int32_t>(skip_if_error), bank, coords, shift);
+                       best, cut, err, static_cast<int32_t>(skip_if_error), bank, coords, shift,
+                       job);
     return hipGetLastError();
 }
 
