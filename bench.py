@@ -324,7 +324,7 @@ def main():
     ap.add_argument("--serve-events", type=int, default=40000, help="0 skips the serving run")
     ap.add_argument("--serve-warmup", type=int, default=5000)
     ap.add_argument("--serve-rate", type=float, default=100e3)
-    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--no-kept-only", action="store_true", help="skip the kept-only mode run")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default launch shape instead of the autotuned one")
