@@ -31,6 +31,15 @@ INT_OPS_PER_COMBO = 30 + 6 + 6 + 3 + 2 + 1
 METRIC = "fitted combinations/s and p50/p99 event latency (µs), batched vs plain"
 
 
+def int_ops(n_combos, kernel_ms):
+    """The fused kernel's algorithmic integer operations per second against the VALU peak (a
+    second view beside the HBM roofline: the fit's arithmetic, not its bytes)."""
+    achieved = INT_OPS_PER_COMBO * n_combos / (kernel_ms * 1e-3) / 1e12
+    return dict(bound="alu", achieved=round(achieved, 3), peak=round(INT_PEAK_TOPS, 1),
+                unit="Tops/s", frac=round(achieved / INT_PEAK_TOPS, 4), kernel="k_fused",
+                ops_per_combination=INT_OPS_PER_COMBO)
+
+
 PROFILES = os.path.join(ROOT, "profiles")
 # sources the fused kernel is compiled from: recorded HBM counters are valid while these match
 FUSED_SOURCES = [os.path.join(ROOT, "paper_1312_0917_amd", "csrc", f)
@@ -157,7 +166,8 @@ def measure_large(config, n_events, passes, tune, bank, workers=16):
                              frac=round(ach / HBM_PEAK_GBS, 4),
                              traffic=recorded_traffic(config, n_events), kernel="k_fused",
                              kernel_ms=round(k_ms, 4), algorithmic_bytes=alg,
-                             bytes_per_combination=round(alg / n_combos, 3)))
+                             bytes_per_combination=round(alg / n_combos, 3)),
+               int_ops=int_ops(n_combos, k_ms))
     del runner
     torch.cuda.empty_cache()
     return out
@@ -553,7 +563,8 @@ def main():
                               wg_size=t.wg_size, wgs_per_cu=t.wgs_per_cu, schedule=t.schedule),
                     autotune=tuned,
                     device=dev_name),
-        roofline=roofline, cpu_baseline=cpu, kept_only=kept_only,
+        roofline=roofline, int_ops=int_ops(n_combos, k_ms), cpu_baseline=cpu,
+        kept_only=kept_only,
         event_per_workgroup=events_schedule, plain=plain,
         batches_in_flight=in_flight,
         uneven_autotuned=uneven,
