@@ -626,7 +626,8 @@ __device__ void fit_slot(const FArgs &a, const Stage &S, int r, int32_t ci, int6
 // with its own road's constants, so that every combination is written by exactly one lane.
 // Fitting the listed groups first lets the main pass complete their cache lines while the
 // lines are still in L2 (the other order leaves 16-byte holes that are filled too late and
-// reach HBM twice: 1.37x the algorithmic writes at c2 against 1.18x when it was measured).
+// reach HBM twice: 1.37x the algorithmic writes against 1.18x on a batch of 3000 events of
+// 64 roads, about 32 combinations each, when it was measured).
 template <bool FOLD, int REC>
 __device__ void consume_listed(const FArgs &a, Stage &S) {
     const int32_t cs = S.cs, ce = S.ce, g_lo = S.g_lo, g_hi = S.g_hi;
@@ -833,15 +834,16 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG == 256 ? 
     // Workgroups sharing a CU: equal priorities issue oldest first, and the dispatcher hands
     // out blocks 0 .. num_cus - 1 one per CU before the next num_cus, so the last-dispatched
     // workgroup of a CU (slot = blockIdx.x / num_cus) fitted its chunks about 20 % slower and
-    // ended 4-5 us after the first at c2; the kernel waits for it.  The compute priority rotates
-    // over the slots from chunk to chunk (youngest highest first), so the workgroups of a CU
-    // take turns; all waves of a workgroup share one level.
+    // ended 4-5 us after the first on 3000 events of 64 roads; the kernel waits for it.  The
+    // compute priority rotates over the slots from chunk to chunk (youngest highest first), so
+    // the workgroups of a CU take turns; all waves of a workgroup share one level.
     const int slot = static_cast<int>(blockIdx.x) / (a.num_cus > 0 ? a.num_cus : 1);
     int iter = 0;
     while (!S[cur].done) {
         // The loader runs at the top priority while it stages: its chain of dependent loads
         // and LDS writes sets the pace of the pipeline, and on its SIMD it would otherwise wait
-        // for issue slots behind the compute waves' arithmetic (about 2 % at c2 and c5).
+        // for issue slots behind the compute waves' arithmetic (about 2 % with roads of ~32 and
+        // of ~100 combinations).
         if (wave == 0) {
             __builtin_amdgcn_s_setprio(3);
             produce(a, S[cur ^ 1], L, n_roads, n_combos, n_tiles, T, qlmask);
