@@ -14,8 +14,9 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
-import re
 import os
+import re
+import subprocess
 import sys
 import time
 
@@ -31,39 +32,47 @@ INT_OPS_PER_COMBO = 30 + 6 + 6 + 3 + 2 + 1
 METRIC = "fitted combinations/s and p50/p99 event latency (µs), batched vs plain"
 
 
-def int_ops(n_combos, kernel_ms):
-    """The fused kernel's algorithmic integer operations per second against the VALU peak (a
-    second view beside the HBM roofline: the fit's arithmetic, not its bytes)."""
+def int_ops(n_combos, kernel_ms, tune):
+    """The dominant kernel's algorithmic integer operations per second against the VALU peak
+    (a second view beside the HBM roofline: the fit's arithmetic, not its bytes)."""
     achieved = INT_OPS_PER_COMBO * n_combos / (kernel_ms * 1e-3) / 1e12
     return dict(bound="alu", achieved=round(achieved, 3), peak=round(INT_PEAK_TOPS, 1),
-                unit="Tops/s", frac=round(achieved / INT_PEAK_TOPS, 4), kernel="k_fused",
-                ops_per_combination=INT_OPS_PER_COMBO)
+                unit="Tops/s", frac=round(achieved / INT_PEAK_TOPS, 4),
+                kernel=kernel_name(tune), ops_per_combination=INT_OPS_PER_COMBO)
 
 
 PROFILES = os.path.join(ROOT, "profiles")
-# sources the fused kernel is compiled from: recorded HBM counters are valid while these match
-FUSED_SOURCES = [os.path.join(ROOT, "paper_1312_0917_amd", "csrc", f)
-                 for f in ("svt_fused.hip", "svt_common.h")]
+CSRC = os.path.join(ROOT, "paper_1312_0917_amd", "csrc")
+# sources each timed kernel is compiled from: recorded HBM counters are valid while these match
+KERNEL_SOURCES = {
+    "k_fused": ["svt_fused.hip", "svt_fit.h", "svt_common.h"],
+    "k_onepass": ["svt_onepass.hip", "svt_fit.h", "svt_common.h"],
+    "k_fit_events": ["svt_events.hip", "svt_common.h"],
+}
 
 
-def fused_source_digest():
+def kernel_source_digest(kernel):
     h = hashlib.sha1()
-    for f in FUSED_SOURCES:
-        h.update(open(f, "rb").read())
+    for f in KERNEL_SOURCES[kernel]:
+        path = os.path.join(CSRC, f)
+        if os.path.exists(path):
+            h.update(open(path, "rb").read())
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(config, n_events):
-    """HBM bytes per launch of the fused kernel from the committed counter summary for this
+def recorded_traffic(config, n_events, tune):
+    """HBM bytes per launch of the timed kernel from the committed counter summary for this
     workload (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each scaled by what the counter
-    reads for a plain copy of known size).  None when there is no summary for the workload or
-    the kernel's sources changed since the counters were taken."""
-    path = os.path.join(PROFILES, f"k_fused_{config}_hbm_counters.md")
-    if not os.path.exists(path):
+    reads for a plain copy of known size).  None when there is no summary for the kernel and
+    workload, or the kernel's sources changed since the counters were taken."""
+    kernel = kernel_name(tune)
+    path = os.path.join(PROFILES, f"{kernel}_{config}_hbm_counters.md")
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
         return None
     kv = dict(re.findall(r"^([a-z_0-9]+): (\S+)\s*$", open(path).read(), flags=re.M))
     try:
-        if kv["kernel_source_sha1"] != fused_source_digest() or int(kv["events"]) != n_events:
+        if kv["kernel_source_sha1"] != kernel_source_digest(kernel) or \
+                int(kv["events"]) != n_events:
             return None
         fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
         write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])
@@ -124,29 +133,24 @@ def fused_kernel_ms(runner, steps, warmup):
     return float(np.mean(kms))
 
 
-def measure_large(config, n_events, passes, tune, bank, workers=16):
-    """Max-scale run: whole batch resident in HBM, graph replays, fused-kernel roofline."""
+def measure_large(ls, passes, tune, bank):
+    """Max-scale run: whole batch resident in HBM, graph replays, kernel and pass rooflines."""
     import torch
 
-    import oracle
     from paper_1312_0917_amd import _lib as L
     from paper_1312_0917_amd import pipeline as P
     from paper_1312_0917_amd import synth
 
-    log(f"generating {config} ({n_events} events)")
-    sample = synth.make_sample(config, bank=bank, n_events=n_events, workers=workers)
-    cut = synth.config_chi2_cut(config)
-    n_words, n_roads = len(sample.words), sample.n_roads
-    n_combos = sample.expected_combos()
+    cut = synth.config_chi2_cut("c5")
+    n_words, n_roads, n_combos = len(ls.words), ls.n_roads, ls.combos
     runner = P.BatchRunner(L.make_config(chi2_cut=cut), P.device_bank(bank.f, bank.q), n_words,
                            n_roads, n_combos, kept_cap=0, tune=tune, graph=True, with_c=False)
-    runner.load(P.words_tensor(sample.words))
-    del sample
+    runner.load(P.words_tensor(ls.words))
     runner.run()
     torch.cuda.synchronize()
     sz = runner.sizes()
     assert sz["n_combos"] == n_combos and runner.error()[0] == 0, (sz, runner.error())
-    log(f"{config}: {passes} timed passes over {n_combos} combinations")
+    log(f"c5: {passes} timed passes over {n_combos} combinations")
     t0 = time.perf_counter()
     for _ in range(passes):
         runner.run()
@@ -154,58 +158,53 @@ def measure_large(config, n_events, passes, tune, bank, workers=16):
     dt = (time.perf_counter() - t0) / passes
     k_ms = fused_kernel_ms(runner, passes, 1)
     L.svt_release_graphs()
-    alg = algorithmic_bytes(n_combos, n_words, n_roads)
-    ach = alg / (k_ms * 1e-3) / 1e9
-    out = dict(workload=f"{config}: {n_events} events, {n_roads} roads, {n_words} hit words, "
+    out = dict(workload=f"c5: {ls.n_events} events, {n_roads} roads, {n_words} hit words, "
                         f"{n_combos} combinations",
                value=n_combos / dt, unit="fitted combinations/s", ms_per_pass=round(dt * 1e3, 4),
-               passes=passes, tune=dict(tile_combos=tune.tile_combos, chunk_roads=tune.chunk_roads,
-                                        wg_size=tune.wg_size, wgs_per_cu=tune.wgs_per_cu,
-                                        schedule=tune.schedule),
-               roofline=dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                             frac=round(ach / HBM_PEAK_GBS, 4),
-                             traffic=recorded_traffic(config, n_events), kernel="k_fused",
-                             kernel_ms=round(k_ms, 4), algorithmic_bytes=alg,
-                             bytes_per_combination=round(alg / n_combos, 3)),
-               int_ops=int_ops(n_combos, k_ms))
+               passes=passes, tune=tune_dict(tune),
+               roofline=roofline_of(tune, n_combos, n_words, n_roads, k_ms, dt * 1e3,
+                                    recorded_traffic("c5", ls.n_events, tune)),
+               int_ops=int_ops(n_combos, k_ms, tune))
     del runner
     torch.cuda.empty_cache()
     return out
 
 
-def measure_uneven(bank, steps, log_fn):
+def tune_dict(t):
+    return dict(tile_combos=t.tile_combos, chunk_roads=t.chunk_roads, wg_size=t.wg_size,
+                wgs_per_cu=t.wgs_per_cu, schedule=t.schedule)
+
+
+def measure_uneven(sample, bank, log_fn):
     """Uneven batch in one persistent launch (8192 events, geometric roads/event, heavy-tailed
     hits per layer): the autotuner times every launch shape and keeps the fastest."""
-    import torch
-
-    import oracle
     from paper_1312_0917_amd import _lib as L
     from paper_1312_0917_amd import pipeline as P
     from paper_1312_0917_amd import synth
     from paper_1312_0917_amd import tune as T
 
-    sample = synth.make_sample("c3", bank=bank)
     cut = synth.config_chi2_cut("c3")
-    st, nr, ne, nc, _ = oracle.count(sample.words, oracle.make_config(chi2_cut=cut))
+    nr, nc = sample.n_roads, sample.expected_combos()
     words = P.words_tensor(sample.words)
     res = T.autotune(words, P.device_bank(bank.f, bank.q), L.make_config(chi2_cut=cut), nr, nc,
-                     steps=steps, cache_path=None, use_cache=False, log=log_fn)
-    default = [row for row in res.table if row[:5] == (4096, 64, 256, 3, 0)]
-    flat = [row[5] for row in res.table if row[4] == 0]
-    events = [row[5] for row in res.table if row[4] == 1]
-    return dict(workload=f"c3: {ne} events, {nr} roads, {len(sample.words)} hit words, "
-                         f"{nc} combinations", best_tune=dict(zip(
-                             ("tile_combos", "chunk_roads", "wg_size", "wgs_per_cu", "schedule"),
-                             T.tune_tuple(res.tune))),
+                     cache_path=None, use_cache=False, log=log_fn)
+    default = [row for row in res.table if row[:5] == T.tune_tuple(L.svt_tune_resolve(None))]
+    by_sched = {}
+    for row in res.table:
+        by_sched[row[4]] = min(by_sched.get(row[4], 1e30), row[5])
+    return dict(workload=f"c3: {sample.n_events} events, {nr} roads, {len(sample.words)} hit "
+                         f"words, {nc} combinations",
+                best_tune=dict(zip(("tile_combos", "chunk_roads", "wg_size", "wgs_per_cu",
+                                    "schedule"), T.tune_tuple(res.tune))),
                 ms_per_pass_best=round(res.ms_per_pass, 5),
                 ms_per_pass_default=default[0][5] if default else None,
                 value=nc / (res.ms_per_pass * 1e-3), unit="fitted combinations/s",
-                candidates=len(res.table), all_outputs_identical=True,
-                ablation_ms_per_pass=dict(flat_tiles_best=min(flat) if flat else None,
-                                          event_per_workgroup_best=min(events) if events else None))
+                candidates=len(res.table), statistic=res.statistic,
+                all_outputs_identical=True,
+                best_ms_per_pass_by_schedule={str(k): v for k, v in sorted(by_sched.items())})
 
 
-def measure_serving(bank, n_events, warmup_events, rate_hz, n_slots, max_events, tune, workers):
+def measure_serving(sample, bank, warmup_events, rate_hz, n_slots, max_events, tune):
     """Poisson stream of events through the continuous-batching loop, fused path and plain path
     fed the same schedule; latency from arrival to results on the host (H2D and D2H included)."""
     import numpy as np
@@ -215,7 +214,7 @@ def measure_serving(bank, n_events, warmup_events, rate_hz, n_slots, max_events,
     from paper_1312_0917_amd import pipeline as P
     from paper_1312_0917_amd import serve, synth
 
-    sample = synth.make_sample("c4", bank=bank, n_events=n_events, workers=workers)
+    n_events = sample.n_events
     arrivals = synth.poisson_arrivals(n_events, rate_hz, seed=3)
     st = serve.EventStream(sample.words, sample.event_word_begin, arrivals)
     mean_w = len(sample.words) / n_events
@@ -250,14 +249,13 @@ def measure_serving(bank, n_events, warmup_events, rate_hz, n_slots, max_events,
                 batched=out["mapped"], batched_copy=out["copy"], plain=plain)
 
 
-def measure_transfer(bank, tune, reps, workers):
+def measure_transfer(sample, bank, tune, reps):
     """Packet latency with pageable, pinned and mapped input (serving-shaped events)."""
     import numpy as np
     from paper_1312_0917_amd import _lib as L
     from paper_1312_0917_amd import pipeline as P
     from paper_1312_0917_amd import synth, transfer
 
-    sample = synth.make_sample("c4", n_events=10000, bank=bank, workers=workers)
     combos = np.prod(sample.road_nhits.astype(np.int64), axis=1)
     pts = transfer.study(sample.words, sample.event_word_begin, sample.road_event, combos,
                          L.make_config(chi2_cut=synth.config_chi2_cut("c4")),
@@ -302,13 +300,161 @@ def measure_kept_only(gcfg, dbank, words, n_words, n_roads, n_combos, tune, step
                               ops_per_combination=INT_OPS_PER_COMBO))
 
 
-def run_cpu_baseline(sample, bank, cfg, seconds):
+def cpu_host():
+    """Host CPU description for the baseline record: model, logical CPUs, and the CPUs this
+    process may run on."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return dict(model=model, nproc=os.cpu_count(), usable_cpus=usable)
+
+
+def run_cpu_baseline(sample, bank, cfg, seconds, threads):
+    """The oracle as it stands, built -O3 -march=native on this host: serially on one core
+    (the paper's serial baseline), then with the batch cut into event ranges that run on
+    `threads` cores at once (the paper's one-event-per-core many-core scheme; events are
+    independent).  Host-only work: call before the GPU runtime starts (it runs a compiler)."""
+    import tempfile
+
     import oracle
 
-    sec, reps, nc = oracle.time_run(sample.words, bank.f, bank.q, cfg, min_seconds=seconds)
-    return dict(value=nc / sec, unit="fitted combinations/s", cores=1, kind="oracle",
-                sample=f"whole batch ({nc} combinations), {reps} full oracle runs in "
-                       f"{sec * reps:.1f} s, single thread, all outputs")
+    flags = "-O3 -march=x86-64-v3"
+    try:
+        lib = oracle.build_native(os.path.join(tempfile.mkdtemp(prefix="svt_oracle_"),
+                                               "libsvt_oracle_native.so"))
+        oracle.use_library(lib)
+        flags = "-O3 -march=native"
+    except (OSError, subprocess.CalledProcessError) as e:  # no compiler: the portable build
+        log(f"native oracle build failed ({e}); timing the portable build")
+    host = cpu_host()
+    sec1, reps1, nc = oracle.time_run(sample.words, bank.f, bank.q, cfg, min_seconds=seconds)
+    secn, repsn, ncn = oracle.time_event_ranges(sample.words, sample.event_word_begin, bank.f,
+                                                bank.q, cfg, threads=threads,
+                                                min_seconds=seconds)
+    assert ncn == nc
+    return dict(value=nc / secn, unit="fitted combinations/s", cores=threads, kind="oracle",
+                sample=f"whole batch ({nc} combinations, all outputs) cut into "
+                       f"{4 * threads} event ranges run by {threads} threads at once, "
+                       f"{repsn} runs in {secn * repsn:.1f} s",
+                serial=dict(value=nc / sec1, cores=1, runs=reps1,
+                            seconds=round(sec1 * reps1, 2)),
+                all_cores_over_serial=round(sec1 / secn, 2),
+                compiler_flags=flags, cpu_model=host["model"], nproc=host["nproc"],
+                usable_cpus=host["usable_cpus"])
+
+
+def kernel_name(tune):
+    return {1: "k_fit_events", 2: "k_onepass", 3: "k_fused"}.get(tune.schedule, "?")
+
+
+def kernel_bytes(tune, n_combos, n_words, n_roads):
+    """Algorithmic bytes of the timed kernel alone.  The one-pass kernel is the whole pass
+    (the words in, records and best tracks out).  The persistent kernel of the two-kernel
+    pass reads what the pre-pass wrote -- 2 B of grouped coordinate per word and 28 B of road
+    table per road (hit_begin, combo_begin, nhits, ncombo, set) -- and writes the records;
+    the best tracks are written by the finalize launch after it."""
+    if tune.schedule == 2:
+        return algorithmic_bytes(n_combos, n_words, n_roads)
+    return 21 * n_combos + 2 * n_words + 28 * n_roads
+
+
+def roofline_of(tune, n_combos, n_words, n_roads, kernel_ms, pass_ms, traffic):
+    kb = kernel_bytes(tune, n_combos, n_words, n_roads)
+    alg = algorithmic_bytes(n_combos, n_words, n_roads)
+    ach = kb / (kernel_ms * 1e-3) / 1e9
+    pas = alg / (pass_ms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic,
+                traffic_over_algorithmic=round(traffic / kb, 3) if traffic else None,
+                kernel=kernel_name(tune), kernel_ms=round(kernel_ms, 5),
+                kernel_algorithmic_bytes=kb,
+                pass_level=dict(achieved=round(pas, 1), frac=round(pas / HBM_PEAK_GBS, 4),
+                                ms=round(pass_ms, 5), algorithmic_bytes=alg,
+                                bytes_per_combination=round(alg / n_combos, 3)))
+
+
+def measure_small(sample, bank, cut, reps, ora_s):
+    """The paper's low-count regime on the 100-event workload: the batched pass with words
+    resident, the batched pass including the copy of the words in and the per-road results
+    out, the plain path, each `reps` times (the paper's 100 repetitions), beside the oracle."""
+    import numpy as np
+    import torch
+
+    from paper_1312_0917_amd import _lib as L
+    from paper_1312_0917_amd import pipeline as P
+
+    gcfg = L.make_config(chi2_cut=cut)
+    dbank = P.device_bank(bank.f, bank.q)
+    nw, nr, nc = len(sample.words), sample.n_roads, sample.expected_combos()
+    words = P.words_tensor(sample.words)
+    runner = P.BatchRunner(gcfg, dbank, nw, nr, nc, kept_cap=0, graph=True, with_c=False)
+    runner.load(words)
+    for _ in range(5):
+        runner.run()
+    torch.cuda.synchronize()
+    assert runner.error() == (0, -1) and runner.sizes()["n_combos"] == nc
+    t = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        runner.run()
+        runner.stream.synchronize()
+        t.append(time.perf_counter() - t0)
+    resident = float(np.median(t))
+    pinned = torch.empty(nw, dtype=torch.int32, pin_memory=True)
+    pinned.numpy().view(np.uint32)[:] = sample.words
+    h_best = {k: torch.empty(nr, dtype=v.dtype, pin_memory=True) for k, v in runner.best.items()}
+    t = []
+    for _ in range(reps + 5):
+        t0 = time.perf_counter()
+        with torch.cuda.stream(runner.stream):
+            runner.words[:nw].copy_(pinned, non_blocking=True)
+        runner.run()
+        with torch.cuda.stream(runner.stream):
+            for k in h_best:
+                h_best[k].copy_(runner.best[k][:nr], non_blocking=True)
+        runner.stream.synchronize()
+        t.append(time.perf_counter() - t0)
+    with_io = float(np.median(t[5:]))
+    L.svt_release_graphs()
+    del runner
+    pr = P.PlainRunner(gcfg, dbank, with_c=False, want_kept=False)
+    for _ in range(5):
+        pr.run(words)
+    torch.cuda.synchronize()
+    t = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        pr.run(words)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter() - t0)
+    plain = float(np.median(t))
+    us = lambda x: round(x * 1e6, 2)
+    return dict(workload=f"c1: {sample.n_events} events, {nr} roads, {nw} hit words, "
+                         f"{nc} combinations",
+                reps=reps, statistic="median",
+                batched=dict(us_per_pass=us(resident), value=nc / resident),
+                batched_with_io=dict(us_per_pass=us(with_io), value=nc / with_io,
+                                     io="words in from page-locked memory, the 6 per-road "
+                                        "best-track arrays out"),
+                plain=dict(us_per_pass=us(plain), value=nc / plain),
+                oracle=dict(us_per_pass=us(ora_s), value=nc / ora_s, cores=1),
+                unit="fitted combinations/s")
+
+
+def slim(sample):
+    """Only what the GPU runs need of a large sample: its words and sizes."""
+    import types
+    return types.SimpleNamespace(words=sample.words, n_roads=sample.n_roads,
+                                 n_events=sample.n_events, combos=sample.expected_combos())
 
 
 def main():
@@ -319,16 +465,23 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--events", type=int, default=0, help="override the workload's event count")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the all-core oracle baseline (0: usable CPUs, at most 16)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the 100-event workload")
+    ap.add_argument("--small-reps", type=int, default=100)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--occ", type=int, default=0)
+    ap.add_argument("--schedule", type=int, default=-1,
+                    help="launch schedule (0 two-kernel pass, 1 event per workgroup, 2 one "
+                         "pass); default: the built-in or autotuned one")
     ap.add_argument("--large-events", type=int, default=10000,
                     help="events of the max-scale run (10000 x 2048 roads); 0 skips it")
     ap.add_argument("--large-passes", type=int, default=5)
-    ap.add_argument("--workers", type=int, default=16, help="processes drawing large samples")
+    ap.add_argument("--workers", type=int, default=16, help="threads drawing large samples")
     ap.add_argument("--no-graph", action="store_true", help="direct launches instead of replays")
     ap.add_argument("--no-uneven", action="store_true", help="skip the autotuned uneven batch")
     ap.add_argument("--serve-events", type=int, default=40000, help="0 skips the serving run")
@@ -354,35 +507,67 @@ def main():
         copy_calibration()
         return
 
+    # ---- host-side work first: every sample is drawn and the CPU baselines are timed before
+    # the GPU runtime starts, so no compiler or worker runs beside a GPU-holding process -------
     import numpy as np
-    import torch
 
     import oracle
+    from paper_1312_0917_amd import synth
+
+    bank = synth.make_bank()
+    n_ev = args.events or synth.CONFIGS[args.config]["n_events"]
+    log(f"drawing {args.config} ({n_ev} events)")
+    sample = synth.make_sample(args.config, bank=bank, n_events=n_ev, workers=args.workers)
+    cut = synth.config_chi2_cut(args.config)
+    cfg = oracle.make_config(chi2_cut=cut)
+    small = synth.make_sample("c1", bank=bank) if not args.no_small else None
+    uneven_s = synth.make_sample("c3", bank=bank, workers=args.workers) \
+        if not args.no_uneven else None
+    serve_s = synth.make_sample("c4", bank=bank, n_events=args.serve_events,
+                                workers=args.workers) if args.serve_events > 0 else None
+    transfer_s = synth.make_sample("c4", bank=bank, n_events=10000, workers=args.workers) \
+        if args.transfer_reps > 0 else None
+    large_s = None
+    if args.large_events > 0:
+        log(f"drawing c5 ({args.large_events} events)")
+        large_s = slim(synth.make_sample("c5", bank=bank, n_events=args.large_events,
+                                         workers=args.workers))
+    cpu = None
+    host = cpu_host()
+    threads = args.cpu_threads or min(16, host["usable_cpus"])
+    if not args.no_cpu:
+        log(f"cpu oracle baseline (~{2 * args.cpu_seconds:.0f} s: 1 core, then {threads})")
+        cpu = run_cpu_baseline(sample, bank, cfg, args.cpu_seconds, threads)
+    small_ora = None
+    if small is not None:
+        sc = oracle.make_config(chi2_cut=synth.config_chi2_cut("c1"))
+        oracle.run(small.words, bank.f, bank.q, sc)
+        ts = []
+        for _ in range(args.small_reps):
+            t0 = time.perf_counter()
+            oracle.run(small.words, bank.f, bank.q, sc)
+            ts.append(time.perf_counter() - t0)
+        small_ora = float(np.median(ts))
+
+    # ---- GPU ----------------------------------------------------------------------------------
+    import torch
+
     from paper_1312_0917_amd import _lib as L
     from paper_1312_0917_amd import pipeline as P
-    from paper_1312_0917_amd import synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     dev_name = torch.cuda.get_device_name(0)
     K, W = args.steps, args.warmup
 
-    log(f"generating {args.config}")
-    bank = synth.make_bank()
-    n_ev = args.events or synth.CONFIGS[args.config]["n_events"]
-    big = synth.expected_size(args.config)["words"] * n_ev / synth.CONFIGS[args.config]["n_events"] > 5e7
-    sample = synth.make_sample(args.config, bank=bank, n_events=n_ev,
-                               workers=args.workers if big else 1)
-    cut = synth.config_chi2_cut(args.config)
-    cfg = oracle.make_config(chi2_cut=cut)
-    st, n_roads, n_events, n_combos, _ = oracle.count(sample.words, cfg)
-    assert st == 0
-    n_words = len(sample.words)
+    n_words, n_roads, n_events = len(sample.words), sample.n_roads, sample.n_events
+    n_combos = sample.expected_combos()  # the generator's own record of the batch
     gcfg = L.make_config(chi2_cut=cut)
     dbank = P.device_bank(bank.f, bank.q)
     words = P.words_tensor(sample.words)
-    explicit_tune = any((args.tile, args.chunk, args.wg, args.occ))
-    tune = L.svt_tune_resolve(L.make_tune(args.tile, args.chunk, args.wg, args.occ))
+    explicit_tune = any((args.tile, args.chunk, args.wg, args.occ)) or args.schedule >= 0
+    tune = L.svt_tune_resolve(L.make_tune(args.tile, args.chunk, args.wg, args.occ,
+                                          max(args.schedule, 0)))
     default_tune = L.svt_tune_resolve(None)
     tuned = None
     if not explicit_tune and not args.no_autotune:
@@ -390,10 +575,11 @@ def main():
         # same bytes); the timed steps below then use the winner
         from paper_1312_0917_amd import tune as T
         log("autotuning the batch")
-        res = T.autotune(words, dbank, gcfg, n_roads, n_combos, steps=10, cache_path=None,
+        res = T.autotune(words, dbank, gcfg, n_roads, n_combos, cache_path=None,
                          use_cache=False)
         tune = res.tune
-        tuned = dict(candidates=len(res.table), best_ms_per_pass=round(res.ms_per_pass, 5))
+        tuned = dict(candidates=len(res.table), best_ms_per_pass=round(res.ms_per_pass, 5),
+                     statistic=res.statistic)
 
     # ---- batched path: resident buffers, graph replay -------------------------------------
     runner = P.BatchRunner(gcfg, dbank, n_words, n_roads, n_combos, kept_cap=0, tune=tune,
@@ -415,17 +601,11 @@ def main():
     batch_s = (t1 - t0) / K
     value = n_combos / batch_s
 
-    # ---- fused kernel alone: HIP events on the runner's stream around each launch ---------
-    log("fused kernel timing")
+    # ---- the dominant kernel alone: HIP events on the runner's stream around its launch ----
+    log("kernel timing")
     k_ms = fused_kernel_ms(runner, K, W)
-    alg = algorithmic_bytes(n_combos, n_words, n_roads)
-    achieved = alg / (k_ms * 1e-3) / 1e9
-    traffic = recorded_traffic(args.config, n_events)
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    traffic_over_algorithmic=round(traffic / alg, 3) if traffic else None,
-                    kernel="k_fused", kernel_ms=round(k_ms, 5), algorithmic_bytes=alg,
-                    bytes_per_combination=round(alg / n_combos, 3))
+    traffic = recorded_traffic(args.config, n_events, tune)
+    roofline = roofline_of(tune, n_combos, n_words, n_roads, k_ms, batch_s * 1e3, traffic)
 
     # ---- several batches in flight: more runners, each with its own stream and graph -------
     # (not the headline: `value` is one pass at a time.  With independent batches queued on
@@ -516,39 +696,38 @@ def main():
                      batched_over_plain=round(plain_s / batch_s, 2))
         del pr
 
+    small_res = None
+    if small is not None:
+        log(f"c1: {args.small_reps} repetitions of each path")
+        small_res = measure_small(small, bank, synth.config_chi2_cut("c1"), args.small_reps,
+                                  small_ora)
+
     uneven = None
-    if not args.no_uneven:
+    if uneven_s is not None:
         log("uneven batch: autotuning")
-        uneven = measure_uneven(bank, 10, log)
+        uneven = measure_uneven(uneven_s, bank, log)
 
     serving = None
-    if args.serve_events > 0:
+    if serve_s is not None:
         log(f"serving: {args.serve_events} events at {args.serve_rate:.0f} Hz")
         # small batches: the default launch shape (the autotuner's pick is for the big batch)
-        serving = measure_serving(bank, args.serve_events, args.serve_warmup, args.serve_rate,
-                                  args.serve_slots, 256, tune if explicit_tune else default_tune,
-                                  args.workers)
+        serving = measure_serving(serve_s, bank, args.serve_warmup, args.serve_rate,
+                                  args.serve_slots, 256, tune if explicit_tune else default_tune)
 
     transfer = None
-    if args.transfer_reps > 0:
+    if transfer_s is not None:
         log("transfer study")
-        transfer = measure_transfer(bank, tune if explicit_tune else default_tune,
-                                    args.transfer_reps, args.workers)
+        transfer = measure_transfer(transfer_s, bank, tune if explicit_tune else default_tune,
+                                    args.transfer_reps)
 
     large = None
-    if args.large_events > 0:
+    if large_s is not None:
         L.svt_release_graphs()
         del runner
         torch.cuda.empty_cache()
-        large = measure_large("c5", args.large_events, args.large_passes,
-                              tune if explicit_tune else default_tune, bank, args.workers)
+        large = measure_large(large_s, args.large_passes,
+                              tune if explicit_tune else default_tune, bank)
 
-    cpu = None
-    if not args.no_cpu:
-        log(f"cpu oracle baseline (~{args.cpu_seconds:.0f} s)")
-        cpu = run_cpu_baseline(sample, bank, cfg, args.cpu_seconds)
-
-    t = tune
     out = dict(
         metric=METRIC, value=value, unit="fitted combinations/s", n_gpus=1, steps=K, warmup=W,
         ms_per_step=round(batch_s * 1e3, 5), higher_is_better=True, scaling="weak",
@@ -559,12 +738,9 @@ def main():
                     events=n_events, roads=n_roads, words=n_words, combinations=n_combos,
                     chi2_cut=cut, path="svt_process_batch (%s)" % (
                         "direct launches" if args.no_graph else "graph replay"),
-                    tune=dict(tile_combos=t.tile_combos, chunk_roads=t.chunk_roads,
-                              wg_size=t.wg_size, wgs_per_cu=t.wgs_per_cu, schedule=t.schedule),
-                    autotune=tuned,
-                    device=dev_name),
-        roofline=roofline, int_ops=int_ops(n_combos, k_ms), cpu_baseline=cpu,
-        kept_only=kept_only,
+                    tune=tune_dict(tune), autotune=tuned, device=dev_name),
+        roofline=roofline, int_ops=int_ops(n_combos, k_ms, tune), cpu_baseline=cpu,
+        small_batch=small_res, kept_only=kept_only,
         event_per_workgroup=events_schedule, plain=plain,
         batches_in_flight=in_flight,
         uneven_autotuned=uneven,

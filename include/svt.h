@@ -126,15 +126,23 @@ typedef struct svt_best {
 
 /* Launch parameters of the batched pass; zeros pick the built-in defaults. */
 typedef struct svt_tune {
-    int32_t tile_combos;  /* combinations per work tile: 4096 or 8192 */
-    int32_t chunk_roads;  /* roads staged in LDS at once: 64 */
-    int32_t wg_size;      /* 256 or 512 (one loader wave, the rest fit) */
+    int32_t tile_combos;  /* two-kernel schedule: combinations per work tile, 4096 or 8192 */
+    int32_t chunk_roads;  /* two-kernel schedule: roads staged in LDS at once, 64 */
+    int32_t wg_size;      /* two-kernel schedule: 256 or 512 (one loader wave, the rest fit) */
     int32_t wgs_per_cu;   /* persistent workgroups per compute unit, 1..8 */
-    int32_t schedule;     /* 0: persistent fused kernel over flat combination tiles (default);
-                             1: one event per workgroup at a time (the multi-core scheme of
-                             section II-A, kept as an ablation; tile_combos, chunk_roads and
-                             wg_size then only have to be valid values) */
+    int32_t schedule;     /* SVT_SCHEDULE_*; 0 picks the built-in one (one pass).  The fields a
+                             schedule does not use only have to be valid values. */
 } svt_tune;
+/* One persistent kernel that unpacks, combines, fits and selects units of 1024 words, each
+ * workgroup holding its unit's roads, pair tables and best tracks in LDS (the loop nest of
+ * section II-A per unit); the pass is that kernel and a reset of its look-back state. */
+#define SVT_SCHEDULE_ONEPASS 2
+/* One event per workgroup at a time (the multi-core scheme of section II-A, an ablation). */
+#define SVT_SCHEDULE_EVENTS 1
+/* A single-pass pre-pass writes the road table and grouped coordinates, then a persistent
+ * kernel fits flat tiles of tile_combos combinations and a last launch finalizes the best
+ * tracks (four launches per pass). */
+#define SVT_SCHEDULE_TILES 3
 
 /* ---- sizes of the caller-provided scratch ------------------------------------------------ */
 int64_t svt_unpack_workspace(int64_t n_words);
@@ -174,9 +182,17 @@ svt_status svt_fit(const svt_fconst *bank, const svt_config *cfg, const svt_road
                    const int32_t *combo_road, const uint32_t *combo_hits, int64_t n_combos,
                    const svt_fitrec *out, uint64_t *d_err, hipStream_t stream);
 
-/* Stage 4, select: accept[i] = (rec->chi2[i] <= cut); per road n_accept and best track (see
- * above); when kept is non-NULL, the ascending indices of accepted combinations (at most
- * kept_cap written, the count in *d_n_kept). */
+/* Stage 4, select (section II: the fit yields the chi-square of each fitted track, and that
+ * chi-square is what a trigger keeps or rejects a track by).  The paper prints no cut and no
+ * rule for a road's best track; this library's readings are: accept[i] = (rec->chi2[i] <=
+ * chi2_cut), inclusive; the best track of a road is its accepted combination of smallest
+ * chi2, the first in enumeration order (smallest k) among equal chi2, which is what the serial
+ * loop nest of section II-A keeps with a strict "<".  Per road: n_accept and that best track
+ * (k, p0..p2, chi2; none: k = -1, p = INT32_MIN, chi2 = INT64_MAX).  combo_road[n_combos]
+ * (from svt_combine) names each record's road; rec holds the records of svt_fit.  When kept is
+ * non-NULL, the ascending indices of accepted combinations (at most kept_cap written, the
+ * count in *d_n_kept; d_n_kept alone gives the count without the list).  Indices outside the
+ * road table are reported in *d_err (class INDEX, index = combination) and skipped. */
 svt_status svt_select(const svt_config *cfg, const svt_roads *roads, int64_t n_roads,
                       const int32_t *combo_road, const svt_fitrec *rec, int64_t n_combos,
                       uint8_t *accept, const svt_best *best, int64_t *kept, int64_t kept_cap,

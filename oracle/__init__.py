@@ -20,11 +20,23 @@ LIB = os.path.join(HERE, "libsvt_oracle.so")
 OK, ERR_ARG, ERR_LAYER, ERR_HITS, ERR_SET = 0, -1, -2, -3, -6
 
 
-def build() -> str:
-    """Compile the oracle with the host C compiler (plain -O2, no target-specific flags)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", LIB, SRC]
-    subprocess.run(cmd, check=True)
-    return LIB
+# -O3 for a portable x86-64 level: the library is built on one machine and may run on another
+# host CPU, so no -march=native here (build_native() makes that variant on the timing host).
+CFLAGS = ["-O3", "-march=x86-64-v3", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC"]
+
+
+def build(out: str = LIB, native: bool = False) -> str:
+    """Compile the oracle with the host C compiler (no intrinsics; -O3)."""
+    flags = [f if f != "-march=x86-64-v3" else "-march=native" for f in CFLAGS] if native \
+        else CFLAGS
+    subprocess.run(["gcc", *flags, "-o", out, SRC], check=True)
+    return out
+
+
+def build_native(out: str) -> str:
+    """The same source compiled with -O3 -march=native on the host that will run it (for the
+    benchmark's CPU baseline).  Returns the library path."""
+    return build(out, native=True)
 
 
 class _Config(ctypes.Structure):
@@ -47,22 +59,31 @@ class _Out(ctypes.Structure):
 _lib = None
 
 
+def use_library(path: str) -> None:
+    """Load the oracle from another build of the same source (before any other call)."""
+    global _lib
+    _lib = _bind(ctypes.CDLL(path))
+
+
 def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
             build()
-        lib = ctypes.CDLL(LIB)
-        lib.ora_count.restype = ctypes.c_int32
-        lib.ora_count.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(_Config),
-                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
-                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
-        lib.ora_run.restype = ctypes.c_int32
-        lib.ora_run.argtypes = [_P, ctypes.c_int64, _P, _P, ctypes.POINTER(_Config),
-                                ctypes.POINTER(_Out), ctypes.POINTER(ctypes.c_int64),
-                                ctypes.POINTER(ctypes.c_int64)]
-        _lib = lib
+        _lib = _bind(ctypes.CDLL(LIB))
     return _lib
+
+
+def _bind(lib):
+    lib.ora_count.restype = ctypes.c_int32
+    lib.ora_count.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(_Config),
+                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.ora_run.restype = ctypes.c_int32
+    lib.ora_run.argtypes = [_P, ctypes.c_int64, _P, _P, ctypes.POINTER(_Config),
+                            ctypes.POINTER(_Out), ctypes.POINTER(ctypes.c_int64),
+                            ctypes.POINTER(ctypes.c_int64)]
+    return lib
 
 
 def make_config(chi2_cut=256, shift=10, max_hits=8, n_sets=256, n_layers=5) -> dict:
@@ -93,11 +114,15 @@ def count(words: np.ndarray, cfg: dict):
     return st, nr.value, ne.value, nc.value, ei.value
 
 
+ALL_FIELDS = tuple(_OUT_FIELDS)
+
+
 def run(words: np.ndarray, f: np.ndarray, q: np.ndarray, cfg: dict,
-        combos: bool = True, raise_on_error: bool = True) -> dict:
+        combos: bool = True, raise_on_error: bool = True, fields=None) -> dict:
     """Run the whole path on the CPU; returns every output as numpy arrays.
 
     ``combos=False`` skips the per-combination arrays (road table and best tracks only).
+    ``fields``: when given, only these outputs are produced (the oracle skips the others).
     On an input error, raises ``OracleError`` (or returns {"status", "err_index"}).
     """
     lib = _load()
@@ -126,6 +151,8 @@ def run(words: np.ndarray, f: np.ndarray, q: np.ndarray, cfg: dict,
             c0=np.zeros(nc, np.int32), c1=np.zeros(nc, np.int32), c2=np.zeros(nc, np.int32),
             chi2=np.zeros(nc, np.int64), accept=np.zeros(nc, np.uint8),
             kept=np.zeros(nc, np.int64))
+    if fields is not None:
+        res = {k: v for k, v in res.items() if k in fields}
     out = _Out(**{k: (res[k].ctypes.data if (k in res and res[k].size) else None)
                   for k in _OUT_FIELDS})
     nk = ctypes.c_int64()
@@ -137,7 +164,7 @@ def run(words: np.ndarray, f: np.ndarray, q: np.ndarray, cfg: dict,
         if raise_on_error:
             raise OracleError(st, eidx.value)
         return dict(status=st, err_index=eidx.value)
-    if combos:
+    if "kept" in res:
         res["kept"] = res["kept"][:nk.value]
     res.update(status=OK, n_roads=nr, n_events=ne, n_combos=nc, n_kept=nk.value)
     return res
@@ -158,4 +185,55 @@ def time_run(words, f, q, cfg, min_seconds: float = 10.0, max_reps: int = 1000):
         reps += 1
         el = time.perf_counter() - t0
         if el >= min_seconds or reps >= max_reps:
+            return el / reps, reps, nc
+
+
+def run_event_ranges(words: np.ndarray, event_word_begin: np.ndarray, f: np.ndarray,
+                     q: np.ndarray, cfg: dict, chunks, threads: int = 1, fields=None,
+                     consume=None):
+    """Run the oracle on several event ranges of one stream at once (the per-event parallel
+    scheme of the paper's many-core port: events are independent).
+
+    ``chunks`` is a list of (e0, e1) event ranges; range c runs on words
+    event_word_begin[e0] .. event_word_begin[e1] as its own stream, so its road and
+    combination numbers start at 0.  With ``consume(c, result)`` each result is handed over
+    as soon as it exists (in the worker thread) and not kept; otherwise the results are
+    returned in order.  The oracle's C code holds no state, and ctypes releases the
+    interpreter lock during a call, so ``threads`` ranges really run at once.
+    """
+    import concurrent.futures as cf
+
+    def one(c):
+        e0, e1 = chunks[c]
+        w = words[event_word_begin[e0]:event_word_begin[e1]]
+        r = run(w, f, q, cfg, fields=fields)
+        if consume is not None:
+            consume(c, r)
+            return None
+        return r
+
+    if threads <= 1:
+        return [one(c) for c in range(len(chunks))]
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(one, range(len(chunks))))
+
+
+def time_event_ranges(words, event_word_begin, f, q, cfg, threads: int, min_seconds=10.0,
+                      fields=None):
+    """Wall time of the whole stream run as ``threads`` event ranges on ``threads`` threads at
+    once, repeated until ``min_seconds`` pass.  Returns (seconds_per_run, reps, n_combos)."""
+    n_ev = len(event_word_begin) - 1
+    edges = np.linspace(0, n_ev, 4 * threads + 1).round().astype(np.int64)
+    chunks = [(int(a), int(b)) for a, b in zip(edges[:-1], edges[1:]) if b > a]
+    keep = ("p0",) if fields is None else fields
+    run_event_ranges(words, event_word_begin, f, q, cfg, chunks, threads, fields=keep)
+    reps, nc = 0, 0
+    t0 = time.perf_counter()
+    while True:
+        res = run_event_ranges(words, event_word_begin, f, q, cfg, chunks, threads, fields=fields)
+        nc = sum(r["n_combos"] for r in res)
+        del res
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= min_seconds:
             return el / reps, reps, nc

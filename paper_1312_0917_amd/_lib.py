@@ -19,6 +19,9 @@ SVT_ERR_CAPACITY, SVT_ERR_HIP, SVT_ERR_SET = -4, -5, -6
 SVT_NO_ERROR = (1 << 64) - 1
 SVT_BATCH_GRAPH = 1
 SVT_BATCH_KEPT_ONLY = 2
+SVT_SCHEDULE_EVENTS = 1   # one event per workgroup (ablation)
+SVT_SCHEDULE_ONEPASS = 2  # the built-in: one persistent kernel per pass (plus a reset)
+SVT_SCHEDULE_TILES = 3    # pre-pass, persistent kernel over flat tiles, finalize
 SVT_COPY_H2D = 1
 SVT_COPY_D2H = 2
 

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsvt.so")
-SOURCES = ["svt_api.hip", "svt_stages.hip", "svt_fused.hip", "svt_prepass.hip", "svt_events.hip"]
+SOURCES = ["svt_api.hip", "svt_stages.hip", "svt_fused.hip", "svt_prepass.hip", "svt_events.hip",
+           "svt_onepass.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -29,7 +30,8 @@ HIPCC_FLAGS = [
 ]
 # per-source additions.  svt_fused.hip: without the wave-level atomic rewrite, the one-lane
 # ticket fetch returns its value lazily, so no load behind it waits for the contended counter
-FILE_FLAGS = {"svt_fused.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+FILE_FLAGS = {"svt_fused.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
+              "svt_onepass.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
 
 
 def hipcc() -> str:

@@ -78,9 +78,12 @@ BatchWs carve_batch(Carver &c, int64_t word_cap, int64_t road_cap, int64_t combo
     w.n_events = c.take<int64_t>(2);
     w.events_cap = road_cap > 0 ? road_cap : 1;  // every event holds at least one road
     w.efr = c.take<int32_t>(w.events_cap);
-    w.nb = ceil_div(word_cap > 0 ? word_cap : 1, kPrepassBlockWords);
+    // status words for the smaller of the two word-block sizes (the one-pass units)
+    w.nb = ceil_div(word_cap > 0 ? word_cap : 1, kOnepassUnitWords);
     w.status = c.take<int64_t>(2 * w.nb);
-    w.tiles_cap = ceil_div(combo_cap > 0 ? combo_cap : 1, tile) + 1;
+    // tile marks at the smaller of the tile and the kept block (the one-pass kernel marks
+    // kept blocks)
+    w.tiles_cap = ceil_div(combo_cap > 0 ? combo_cap : 1, tile < kKeptBlock ? tile : kKeptBlock) + 1;
     w.tfr = c.take<int32_t>(w.tiles_cap);
     w.kbn = ceil_div(combo_cap > 0 ? combo_cap : 1, kKeptBlock);
     w.kb = c.take<int64_t>(w.kbn);
@@ -89,13 +92,13 @@ BatchWs carve_batch(Carver &c, int64_t word_cap, int64_t road_cap, int64_t combo
 }
 
 svt_tune resolve_tune(const svt_tune *t) {
-    svt_tune r{4096, 64, 256, 3, 0};
+    svt_tune r{4096, 64, 256, 3, SVT_SCHEDULE_ONEPASS};
     if (t) {
         if (t->tile_combos) r.tile_combos = t->tile_combos;
         if (t->chunk_roads) r.chunk_roads = t->chunk_roads;
         if (t->wg_size) r.wg_size = t->wg_size;
         if (t->wgs_per_cu) r.wgs_per_cu = t->wgs_per_cu;
-        r.schedule = t->schedule;
+        if (t->schedule) r.schedule = t->schedule;
     }
     return r;
 }
@@ -376,12 +379,58 @@ static svt_status batch_sequence(const FusedLaunch &f, const BatchWs &w, int64_t
     p.event_cap = w.events_cap;
     p.d_n_events = w.n_events;
     uint64_t *err = f.err;
+    if (f.tune.schedule == SVT_SCHEDULE_ONEPASS) {
+        // reset, the one-pass kernel, and with a kept list its scan and compaction
+        p.nb_cap = w.nb;
+        SVT_TRY(launch_batch_reset(p, kOnepassUnitWords, d_n_kept, d_n_kept ? w.kb : nullptr,
+                                   d_n_kept ? w.kbn : 0, stream));
+        OnepassLaunch o{};
+        o.bank = f.bank;
+        o.cfg = f.cfg;
+        o.words = f.words;
+        o.nw = nw;
+        o.roads = f.roads;
+        o.road_cap = road_cap;
+        o.rec = f.rec;
+        o.accept = f.accept;
+        o.best = f.best;
+        o.combo_cap = combo_cap;
+        o.d_n_roads = p.d_n_roads;
+        o.d_n_combos = p.d_n_combos;
+        o.kb_counts = d_n_kept ? w.kb : nullptr;
+        o.status = w.status;
+        o.nb_cap = w.nb;
+        o.tickets = w.tickets;
+        o.err = err;
+        o.kept_only = f.kept_only;
+        o.coords = w.coords;
+        o.tile_first_road = w.tfr;
+        o.tiles_cap = w.tiles_cap;
+        o.num_cus = f.num_cus;
+        o.wgs_per_cu = f.tune.wgs_per_cu;
+        if (timing) SVT_TRY(hipEventRecord(g_ev_start, stream));
+        SVT_TRY(launch_onepass(o, stream));
+        if (timing) SVT_TRY(hipEventRecord(g_ev_stop, stream));
+        if (d_n_kept) {
+            SVT_TRY(launch_scan(w.kb, 0, 1, nc, kKeptBlock, d_n_kept, nullptr,
+                                kept ? kept_cap : -1, 2, err, true, stream));
+            if (kept && f.kept_only)
+                SVT_TRY(launch_kept_refit(f.accept, nc, nr, w.kbn, w.kb, f.roads, w.tfr,
+                                          kKeptBlock, f.bank, f.cfg.n_sets, f.coords,
+                                          f.cfg.shift, kept, f.rec, kept_cap, err, stream));
+            else if (kept)
+                SVT_TRY(launch_kept_write(f.accept, nc, w.kbn, w.kb, kept, kept_cap, err,
+                                          stream));
+        }
+        return SVT_OK;
+    }
     // (the kept-list block counts are cleared with the rest: the fused kernel adds to them)
-    SVT_TRY(launch_batch_reset(p, d_n_kept, d_n_kept ? w.kb : nullptr, d_n_kept ? w.kbn : 0,
-                               stream));
+    p.nb_cap = ceil_div(word_cap > 0 ? word_cap : 1, kPrepassBlockWords);
+    SVT_TRY(launch_batch_reset(p, kPrepassBlockWords, d_n_kept, d_n_kept ? w.kb : nullptr,
+                               d_n_kept ? w.kbn : 0, stream));
     SVT_TRY(launch_prepass(p, stream));
     if (timing) SVT_TRY(hipEventRecord(g_ev_start, stream));
-    if (f.tune.schedule == 1)
+    if (f.tune.schedule == SVT_SCHEDULE_EVENTS)
         SVT_TRY(launch_fit_events(f, w.efr, w.n_events, w.events_cap, stream));
     else
         SVT_TRY(launch_fused(f, stream));
@@ -402,8 +451,8 @@ static svt_status batch_sequence(const FusedLaunch &f, const BatchWs &w, int64_t
     if (d_n_kept) {
         if (kept && f.kept_only)
             SVT_TRY(launch_kept_refit(f.accept, nc, nr, w.kbn, w.kb, f.roads, w.tfr,
-                                      f.tune.tile_combos, f.bank, f.coords, f.cfg.shift, kept,
-                                      f.rec, kept_cap, err, stream));
+                                      f.tune.tile_combos, f.bank, f.cfg.n_sets, f.coords,
+                                      f.cfg.shift, kept, f.rec, kept_cap, err, stream));
         else if (kept)
             SVT_TRY(launch_kept_write(f.accept, nc, w.kbn, w.kb, kept, kept_cap, err, stream));
     }

@@ -13,6 +13,7 @@ constexpr int kSegThreads = 256;          // threads of the word-segmentation ke
 constexpr int kSegWordsPerThread = 16;
 constexpr int kSegBlockWords = kSegThreads * kSegWordsPerThread;  // 4096 words per block
 constexpr int kPrepassBlockWords = 2048;  // words per block of the batched single-pass pre-pass
+constexpr int kOnepassUnitWords = 1024;   // words per unit of the one-pass kernel
 constexpr int kRoadBlock = 256;           // roads per block in road-table kernels
 constexpr int kKeptBlock = 4096;          // combinations per block of the kept-list compaction
 constexpr int kScanThreads = 1024;        // single-workgroup scan
@@ -26,8 +27,8 @@ __device__ inline uint64_t best_key(int64_t chi2, uint32_t k) {
     if (c > kKeyChiMax) c = kKeyChiMax;
     return (c << kKeyKBits) | k;
 }
-constexpr int kMaxTile = 8192;
-constexpr int64_t kMaxBatchWords = (1ll << 31) - 1;  // batched path: road and event counts fit 31 bits            // combinations per tile of the fused kernel, at most
+constexpr int kMaxTile = 8192;  // combinations per tile of the fused kernel, at most
+constexpr int64_t kMaxBatchWords = (1ll << 31) - 1;  // batched path: road and event counts fit 31 bits
 
 // ---- error word: (class << 56) | index, smallest wins, all ones = none ------------------
 __device__ inline void report(uint64_t *err, uint32_t cls, uint64_t index) {
@@ -175,12 +176,13 @@ hipError_t launch_kept_write(const uint8_t *accept, Sizes n_combos, int64_t grid
 // Kept-only mode: the ascending indices of accepted combinations into kept[] and their fit
 // values, compacted, into rec (entry i for combination kept[i]), fitted again from the grouped
 // coordinates and the constant bank.  tile_first_road / tile_combos locate each block's roads.
+// Does nothing when *err already holds an error (the inputs it reads are then incomplete).
 hipError_t launch_kept_refit(const uint8_t *accept, Sizes n_combos, Sizes n_roads,
                              int64_t grid_blocks, const int64_t *kb_prefix, const svt_roads &roads,
                              const int32_t *tile_first_road, int64_t tile_combos,
-                             const svt_fconst *bank, const int16_t *coords, int32_t shift,
-                             int64_t *kept, const svt_fitrec &rec, int64_t kept_cap,
-                             uint64_t *err, hipStream_t s);
+                             const svt_fconst *bank, int32_t n_sets, const int16_t *coords,
+                             int32_t shift, int64_t *kept, const svt_fitrec &rec,
+                             int64_t kept_cap, uint64_t *err, hipStream_t s);
 
 struct FusedLaunch {
     const svt_fconst *bank;
@@ -254,10 +256,41 @@ struct PrepassLaunch {
     int64_t event_cap;
     int64_t *d_n_events;
 };
-// Clears the error word, both tickets, *d_n_kept (nullable), the status words in use and
-// zero[0 .. n_zero) (the kept-list block counts; nullable).
-hipError_t launch_batch_reset(const PrepassLaunch &p, int64_t *d_n_kept, int64_t *zero,
-                              int64_t n_zero, hipStream_t s);
+// Clears the error word, both tickets, *d_n_kept (nullable), the status words in use (one pair
+// per block_words words of the batch) and zero[0 .. n_zero) (the kept-list block counts;
+// nullable).
+hipError_t launch_batch_reset(const PrepassLaunch &p, int64_t block_words, int64_t *d_n_kept,
+                              int64_t *zero, int64_t n_zero, hipStream_t s);
 hipError_t launch_prepass(const PrepassLaunch &p, hipStream_t s);
+
+// The whole batched pass in one persistent kernel (unpack, combine, fit, select; road table,
+// records and best tracks written from LDS).  Needs the reset of launch_batch_reset with
+// block_words = kOnepassUnitWords first.
+struct OnepassLaunch {
+    const svt_fconst *bank;
+    svt_config cfg;
+    const uint32_t *words;
+    Sizes nw;
+    svt_roads roads;
+    int64_t road_cap;
+    svt_fitrec rec;
+    uint8_t *accept;
+    svt_best best;
+    int64_t combo_cap;
+    int64_t *d_n_roads;
+    int64_t *d_n_combos;
+    int64_t *kb_counts;        // accepted count per kKeptBlock combinations (null: no kept list)
+    int64_t *status;           // 2 * nb_cap look-back status words
+    int64_t nb_cap;            // ceil(word_cap / kOnepassUnitWords)
+    uint32_t *tickets;
+    uint64_t *err;
+    bool kept_only;            // no records; grouped coordinates and block marks for the refit
+    int16_t *coords;           // kept-only: grouped coordinates (word_cap entries)
+    int32_t *tile_first_road;  // kept-only: first road of every kKeptBlock block
+    int64_t tiles_cap;
+    int num_cus;
+    int wgs_per_cu;
+};
+hipError_t launch_onepass(const OnepassLaunch &p, hipStream_t s);
 
 }  // namespace svt

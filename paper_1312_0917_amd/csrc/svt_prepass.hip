@@ -28,7 +28,7 @@
 // wait forever on one that has not been scheduled, and the wait stays bounded.
 #include <cstdlib>
 
-#include "svt_common.h"
+#include "svt_lookback.h"
 
 namespace svt {
 namespace {
@@ -36,35 +36,9 @@ namespace {
 constexpr int kPT = 256;                  // threads per block
 constexpr int kPB = kPrepassBlockWords;   // 2048 words per block
 constexpr int kPW = kPB / kPT;            // 8 words per thread
-constexpr int kTail = 64;                 // words staged past the block's own
+constexpr int kTail = kRoadTail;          // words staged past the block's own
 constexpr int kOff = 4;                   // sw[kOff - 1] = word before the block; the body
                                           // starts 16-byte aligned
-constexpr uint64_t kStAgg = 1ull << 62;
-constexpr uint64_t kStIncl = 2ull << 62;
-constexpr uint64_t kStMask = 3ull << 62;
-// a look-back round computes missing aggregates itself after this long (wall-clock ticks of
-// 10 ns): far beyond any wait on a predecessor that is running
-constexpr uint64_t kLookbackTimeout = 20000;
-constexpr int kLookWindows = 8;           // predecessors read per round: 64 per window
-
-__device__ inline void status_publish(int64_t *p, uint64_t v) {
-    __hip_atomic_store(reinterpret_cast<uint64_t *>(p), v, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// publish v for a block that has published nothing yet (no effect otherwise)
-__device__ inline void status_claim(int64_t *p, uint64_t v) {
-    uint64_t expected = 0;
-    __hip_atomic_compare_exchange_strong(reinterpret_cast<uint64_t *>(p), &expected, v,
-                                         __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline uint64_t status_read(int64_t *p) {
-    return __hip_atomic_load(reinterpret_cast<uint64_t *>(p), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-}
-
 struct PArgs {
     const uint32_t *words;
     Sizes nw;
@@ -88,163 +62,6 @@ struct PArgs {
     int64_t *d_n_events;
 };
 
-__device__ inline int64_t combos_of(uint32_t packed) {
-    int64_t c = 1;
-#pragma unroll
-    for (int l = 0; l < SVT_N_LAYERS; ++l) c *= nh_of(packed, l);
-    return c;
-}
-
-// The aggregate of block p -- roads that start among its words | events that start there << 31,
-// and the combinations of those roads -- computed from the words in global memory by the rules
-// block p applies to its own staged words (a road runs to the next road start among the block's
-// words and its 64-word tail, else to the end of them; longer than n_layers * max_hits words,
-// or more than max_hits hits on a layer, and it has no combinations).  A look-back that has
-// waited too long for block p to publish uses this instead, so that no block can wait forever
-// on one that has not been scheduled.  One wave; lane i takes the block's words 32 i .. 32 i + 31.
-__device__ void block_aggregate(const PArgs &a, int64_t n, int64_t p, uint64_t &agg0,
-                                uint64_t &agg1) {
-    constexpr int kPerLane = kPB / kWaveSize;
-    const int lane = lane_id();
-    const int64_t base = p * kPB;
-    const int nloc = static_cast<int>(n - base < kPB + kTail ? n - base : kPB + kTail);
-    const int nown = nloc < kPB ? nloc : kPB;
-    const int max_len = a.cfg.n_layers * a.cfg.max_hits;
-    int64_t nr = 0, ne = 0, nc = 0;
-    for (int e = 0; e < kPerLane; ++e) {
-        const int j = lane * kPerLane + e;
-        if (j >= nown) break;
-        const uint32_t x = a.words[base + j];
-        const bool first = base + j == 0;
-        const uint32_t px = first ? 0u : a.words[base + j - 1];
-        ne += (first || w_etag(x) != w_etag(px)) ? 1 : 0;
-        if (!(first || w_tags(x) != w_tags(px))) continue;
-        ++nr;
-        uint64_t cnt = 0;  // 8 bits per layer
-        bool over = false;
-        uint32_t prev = x;
-        for (int k = j, len = 0; k < nloc; ++k) {
-            const uint32_t y = a.words[base + k];
-            if (k > j && w_tags(y) != w_tags(prev)) break;  // next road starts
-            if (++len > max_len) {
-                over = true;
-                break;
-            }
-            const uint32_t l = w_layer(y);
-            if (l < SVT_N_LAYERS) cnt += 1ull << (8 * l);
-            prev = y;
-        }
-        uint32_t packed = 0;
-#pragma unroll
-        for (int l = 0; l < SVT_N_LAYERS; ++l) {
-            const uint32_t c = static_cast<uint32_t>((cnt >> (8 * l)) & 0xFF);
-            over |= c > static_cast<uint32_t>(a.cfg.max_hits);
-            packed |= (c & 0xFu) << (4 * l);
-        }
-        if (!over) nc += combos_of(packed);
-    }
-    agg0 = static_cast<uint64_t>(wave_sum(nr)) | (static_cast<uint64_t>(wave_sum(ne)) << 31);
-    agg1 = static_cast<uint64_t>(wave_sum(nc));
-}
-
-// A block's own counts, published as soon as they are known: an aggregate, or for block 0
-// directly its inclusive prefix.  One thread.
-__device__ inline void publish_aggregate(const PArgs &a, int64_t b, uint64_t agg0,
-                                         uint64_t agg1) {
-    const uint64_t flag = b == 0 ? kStIncl : kStAgg;
-    status_publish(a.status + b, flag | agg0);
-    status_publish(a.status + a.nb_cap + b, flag | agg1);
-}
-
-// Exclusive prefixes over blocks 0..b-1 of two status columns at once (col0[i], col1[i] =
-// column 0 and 1 of block i), for a block whose aggregates are already published
-// (publish_aggregate); publishes its inclusive prefixes once known.  Executed by one whole
-// wave; the results are valid in every lane.  One round reads kLookWindows * 64 predecessors
-// of both columns (lane i of window k inspects block top - 64 k - i, so position 0 is the
-// nearest predecessor); each column sums its values up to its nearest block that already has
-// an inclusive value.  Values are opaque sums: counts packed
-// in one word add field by field as long as no field overflows.  A round that has waited
-// a.lookback_timeout wall-clock ticks for predecessors to publish computes their aggregates
-// from the words instead (block_aggregate) and goes on.
-__device__ void look_back2(const PArgs &a, int64_t n, int64_t b, uint64_t agg0, uint64_t agg1,
-                           uint64_t &ex0, uint64_t &ex1) {
-    int64_t *col0 = a.status, *col1 = a.status + a.nb_cap;
-    const int lane = lane_id();
-    ex0 = 0;
-    ex1 = 0;
-    if (b == 0) return;  // its inclusive prefix is its aggregate, already published
-    bool done0 = false, done1 = false;
-    int64_t top = b - 1;
-    uint64_t wait_since = 0;  // start of this round's wait (0: not waiting)
-    while (!(done0 && done1)) {
-        uint64_t v0[kLookWindows], v1[kLookWindows];
-#pragma unroll
-        for (int k = 0; k < kLookWindows; ++k) {
-            const int64_t idx = top - 64 * k - lane;
-            v0[k] = (idx >= 0 && !done0) ? status_read(col0 + idx) : kStIncl;
-            v1[k] = (idx >= 0 && !done1) ? status_read(col1 + idx) : kStIncl;
-        }
-        int f0 = 64 * kLookWindows, f1 = 64 * kLookWindows;  // nearest inclusive positions
-#pragma unroll
-        for (int k = kLookWindows - 1; k >= 0; --k) {
-            const uint64_t m0 = __ballot((v0[k] & kStMask) == kStIncl);
-            const uint64_t m1 = __ballot((v1[k] & kStMask) == kStIncl);
-            if (m0) f0 = 64 * k + __builtin_ctzll(m0);
-            if (m1) f1 = 64 * k + __builtin_ctzll(m1);
-        }
-        bool wait = false;
-#pragma unroll
-        for (int k = 0; k < kLookWindows; ++k) {
-            const int pos = 64 * k + lane;
-            wait |= __ballot(((v0[k] & kStMask) == 0 && pos <= f0) ||
-                             ((v1[k] & kStMask) == 0 && pos <= f1)) != 0;
-        }
-        if (wait) {  // a block at or before a nearest inclusive one has not published yet
-            const uint64_t now = wall_clock64();
-            if (wait_since == 0) wait_since = now;
-            if (now - wait_since < a.lookback_timeout) {
-                __builtin_amdgcn_s_sleep(1);
-                continue;
-            }
-            // Waited long enough: publish every aggregate this round still misses, computed
-            // from the words, then read the round again.  A compare-and-swap from "nothing"
-            // never overwrites what the block itself has published meanwhile (and what it
-            // publishes later is the same aggregate, or its inclusive prefix).
-            int need = (done0 ? -1 : f0) > (done1 ? -1 : f1) ? f0 : f1;  // farthest position
-            need = need < 64 * kLookWindows ? need : 64 * kLookWindows - 1;  // of this round
-            for (int64_t idx = top; idx >= 0 && top - idx <= need; --idx) {
-                const uint64_t s0 = status_read(col0 + idx), s1 = status_read(col1 + idx);
-                if ((s0 & kStMask) != 0 && (s1 & kStMask) != 0) continue;
-                uint64_t g0, g1;
-                block_aggregate(a, n, idx, g0, g1);
-                if (lane == 0) {
-                    status_claim(col0 + idx, kStAgg | g0);
-                    status_claim(col1 + idx, kStAgg | g1);
-                }
-            }
-            wait_since = 0;
-            continue;
-        }
-        wait_since = 0;
-        uint64_t m0 = 0, m1 = 0;
-#pragma unroll
-        for (int k = 0; k < kLookWindows; ++k) {
-            const int pos = 64 * k + lane;
-            if (!done0 && pos <= f0) m0 += v0[k] & ~kStMask;
-            if (!done1 && pos <= f1) m1 += v1[k] & ~kStMask;
-        }
-        ex0 += wave_sum(m0);
-        ex1 += wave_sum(m1);
-        done0 |= f0 < 64 * kLookWindows;
-        done1 |= f1 < 64 * kLookWindows;
-        top -= 64 * kLookWindows;
-    }
-    if (lane == 0) {
-        status_publish(col0 + b, kStIncl | (ex0 + agg0));
-        status_publish(col1 + b, kStIncl | (ex1 + agg1));
-    }
-}
-
 // Per owned road, in LDS: s_road[rl] = first local word (12 bits) | events started in the block
 // up to that word (12 bits) << 12 | the word starts an event << 24; s_info[rl] = hits per layer
 // (4 bits each) | too-many-hits << 20 | no-constant-set << 21.
@@ -263,6 +80,8 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
     const int tid = threadIdx.x;
     const int64_t n = load_size(a.nw);
     const int64_t b = blockIdx.x;
+    const LookbackCtx lc{a.words, n, a.cfg.n_layers, a.cfg.max_hits, a.status, a.nb_cap,
+                         a.lookback_timeout};
     const int64_t nb = (n + kPB - 1) / kPB;
     if (b == 0 && tid == 0 && a.nw.dev && *a.nw.dev > a.nw.cap)
         report(a.err, SVT_ERRCLASS_CAPACITY, 3);
@@ -392,7 +211,7 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
     const uint64_t agg0 = static_cast<uint64_t>(tr) | (static_cast<uint64_t>(te) << 31);
     const uint64_t agg1 = static_cast<uint64_t>(tc);
     // the aggregate is all that later blocks need from this one: publish it before grouping
-    if (tid == 0) publish_aggregate(a, b, agg0, agg1);
+    if (tid == 0) publish_aggregate(lc, b, agg0, agg1);
 
     // ---- grouped coordinates of the roads with combinations (while predecessors finish) ----
     for (int rl = tid; rl < nroads; rl += kPT) {
@@ -428,7 +247,7 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
     // stay below 2^31) ---------------------------------------------------------------------------
     if (tid < kWaveSize) {
         uint64_t p0, p1;
-        look_back2(a, n, b, agg0, agg1, p0, p1);
+        look_back2<kPB>(lc, b, agg0, agg1, p0, p1);
         if (tid == 0) {
             s_pre[0] = static_cast<int64_t>(p0 & 0x7FFFFFFFull);
             s_pre[1] = static_cast<int64_t>(p0 >> 31);
@@ -496,8 +315,8 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
 // kept count, the look-back status words of the blocks this pass will use and, when given,
 // zero[0 .. n_zero) (the kept list's per-block counts, which the fused kernel adds to).
 __global__ void k_batch_reset(uint64_t *err, uint32_t *tickets, int64_t *d_n_kept,
-                              int64_t *status, int64_t nb_cap, Sizes nw, int64_t *zero,
-                              int64_t n_zero) {
+                              int64_t *status, int64_t nb_cap, int64_t block_words, Sizes nw,
+                              int64_t *zero, int64_t n_zero) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *err = SVT_NO_ERROR;
         tickets[0] = 0;
@@ -505,7 +324,7 @@ __global__ void k_batch_reset(uint64_t *err, uint32_t *tickets, int64_t *d_n_kep
         if (d_n_kept) *d_n_kept = 0;
     }
     const int64_t n = load_size(nw);
-    int64_t nb = (n + kPB - 1) / kPB;
+    int64_t nb = (n + block_words - 1) / block_words;
     if (nb > nb_cap) nb = nb_cap;
     for (int64_t i = gtid(); i < nb; i += gstride()) {
         status[i] = 0;
@@ -546,14 +365,14 @@ hipError_t launch_prepass(const PrepassLaunch &p, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch_reset(const PrepassLaunch &p, int64_t *d_n_kept, int64_t *zero,
-                              int64_t n_zero, hipStream_t s) {
+hipError_t launch_batch_reset(const PrepassLaunch &p, int64_t block_words, int64_t *d_n_kept,
+                              int64_t *zero, int64_t n_zero, hipStream_t s) {
     const int64_t items = zero && n_zero > p.nb_cap ? n_zero : p.nb_cap;
     int64_t blocks = (items + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(k_batch_reset, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
-                       p.err, p.tickets, d_n_kept, p.status, p.nb_cap, p.nw, zero,
+                       p.err, p.tickets, d_n_kept, p.status, p.nb_cap, block_words, p.nw, zero,
                        zero ? n_zero : 0);
     return hipGetLastError();
 }

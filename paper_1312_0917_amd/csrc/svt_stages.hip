@@ -610,9 +610,12 @@ __global__ __launch_bounds__(kSegThreads) void k_kept_refit(
     const uint8_t *__restrict__ accept, Sizes n_s, Sizes nr_s,
     const int64_t *__restrict__ kb_prefix, svt_roads roads,
     const int32_t *__restrict__ tile_first_road, int64_t tile_combos,
-    const svt_fconst *__restrict__ bank, const int16_t *__restrict__ coords, int32_t shift,
-    int64_t *kept, svt_fitrec rec, int64_t kept_cap, uint64_t *err) {
+    const svt_fconst *__restrict__ bank, int32_t n_sets, const int16_t *__restrict__ coords,
+    int32_t shift, int64_t *kept, svt_fitrec rec, int64_t kept_cap, uint64_t *err) {
     constexpr int kWaves = kSegThreads / kWaveSize;
+    // After a data or capacity error the accept flags, the tile marks and the road table are
+    // not (all) written: nothing here may be read.
+    if (has_error(err)) return;
     __shared__ int64_t s_cb[kWaves][kKeptRoads];
     __shared__ uint16_t s_acc[kWaves][kKeptBlock];  // accepted offsets inside the block, in order
     const int wv = threadIdx.x / kWaveSize;
@@ -646,6 +649,10 @@ __global__ __launch_bounds__(kSegThreads) void k_kept_refit(
         const int64_t t1 = ((b + 1) * kKeptBlock - 1) / tile_combos + 1;
         const int64_t r_lo = tile_first_road[t0];
         const int64_t r_hi = t1 < n_tiles ? tile_first_road[t1] : n_roads - 1;
+        if (r_lo < 0 || r_hi < r_lo || r_hi >= n_roads) {  // marks inconsistent with the roads
+            if (lane == 0) report(err, SVT_ERRCLASS_INDEX, static_cast<uint64_t>(b * kKeptBlock));
+            continue;
+        }
         const int64_t nloc = r_hi - r_lo + 1;
         const bool staged = nloc <= kKeptRoads;
         int64_t *cb_l = s_cb[wv];
@@ -664,14 +671,15 @@ __global__ __launch_bounds__(kSegThreads) void k_kept_refit(
             }
             const int64_t r = r_lo + lo;
             const int64_t k = i - (staged ? cb_l[lo] : roads.combo_begin[r]);
-            if (k < 0 || k >= roads.ncombo[r]) {
+            const int32_t set = roads.set[r];
+            if (k < 0 || k >= roads.ncombo[r] || set < 0 || set >= n_sets) {
                 report(err, SVT_ERRCLASS_INDEX, static_cast<uint64_t>(i));
                 continue;
             }
             if (pos < kept_cap) {
                 int32_t v[6];
                 const int64_t c2 = refit_combo(bank, coords, shift, roads.nhits[r],
-                                               roads.hit_begin[r], roads.set[r],
+                                               roads.hit_begin[r], set,
                                                static_cast<uint32_t>(k), v, 6);
                 kept[pos] = i;
                 if (rec.p0) rec.p0[pos] = v[0];
@@ -865,14 +873,14 @@ namespace svt {
 hipError_t launch_kept_refit(const uint8_t *accept, Sizes n_combos, Sizes n_roads,
                              int64_t grid_blocks, const int64_t *kb_prefix, const svt_roads &roads,
                              const int32_t *tile_first_road, int64_t tile_combos,
-                             const svt_fconst *bank, const int16_t *coords, int32_t shift,
-                             int64_t *kept, const svt_fitrec &rec, int64_t kept_cap,
-                             uint64_t *err, hipStream_t s) {
+                             const svt_fconst *bank, int32_t n_sets, const int16_t *coords,
+                             int32_t shift, int64_t *kept, const svt_fitrec &rec,
+                             int64_t kept_cap, uint64_t *err, hipStream_t s) {
     // one wave per kept block, four per workgroup
     const int64_t g = clamp_grid((grid_blocks + 3) / 4, 1 << 16);
     hipLaunchKernelGGL(k_kept_refit, dim3(g), dim3(kSegThreads), 0, s, accept, n_combos, n_roads,
-                       kb_prefix, roads, tile_first_road, tile_combos, bank, coords, shift, kept,
-                       rec, kept_cap, err);
+                       kb_prefix, roads, tile_first_road, tile_combos, bank, n_sets, coords,
+                       shift, kept, rec, kept_cap, err);
     return hipGetLastError();
 }
 }  // namespace svt

@@ -21,6 +21,7 @@ roads of one event never share a tag.
 from __future__ import annotations
 
 import dataclasses
+import functools
 import math
 from typing import Optional
 
@@ -267,18 +268,10 @@ def _draw_block(rng, bank: Bank, n_ev: int, ev0: int, roads_spec, hits_spec, tru
                 true_road=true_road, t=t, slot=slot, rpe=rpe)
 
 
-_POOL_BANK = None
-
-
-def _set_pool_bank(bank):
-    global _POOL_BANK
-    _POOL_BANK = bank
-
-
-def _draw_job(job):
+def _draw_job(job, bank: Bank):
     seed, blk, ev0, n, roads, hits, true_frac, layer_major = job
     rng = np.random.default_rng([seed, blk])
-    return _draw_block(rng, _POOL_BANK, n, ev0, roads, hits, true_frac, layer_major)
+    return _draw_block(rng, bank, n, ev0, roads, hits, true_frac, layer_major)
 
 
 def make_sample(config: str | dict, seed: Optional[int] = None, n_events: Optional[int] = None,
@@ -288,7 +281,9 @@ def make_sample(config: str | dict, seed: Optional[int] = None, n_events: Option
 
     Events are drawn in blocks of 256 with child streams ``default_rng([seed, block])``, so a
     prefix of events does not depend on how many events follow it, nor on ``workers`` (blocks
-    drawn in that many processes).
+    drawn by that many threads of this process: numpy's generators and array operations
+    release the interpreter lock, and no child process is started, which matters in a
+    process that already holds the GPU).
     """
     cfg = dict(CONFIGS[config]) if isinstance(config, str) else dict(config)
     seed = cfg["seed"] if seed is None else seed
@@ -296,14 +291,13 @@ def make_sample(config: str | dict, seed: Optional[int] = None, n_events: Option
     bank = make_bank() if bank is None else bank
     jobs = [(seed, blk, ev0, min(EVENTS_PER_BLOCK, n_ev - ev0), cfg["roads"], cfg["hits"],
              true_frac, layer_major) for blk, ev0 in enumerate(range(0, n_ev, EVENTS_PER_BLOCK))]
+    draw = functools.partial(_draw_job, bank=bank)
     if workers > 1 and len(jobs) > 1:
-        import multiprocessing as mp
-        with mp.get_context("fork").Pool(min(workers, len(jobs)),
-                                         initializer=_set_pool_bank, initargs=(bank,)) as pool:
-            parts = pool.map(_draw_job, jobs, chunksize=1)
+        import concurrent.futures as cf
+        with cf.ThreadPoolExecutor(max_workers=min(workers, len(jobs))) as ex:
+            parts = list(ex.map(draw, jobs))
     else:
-        _set_pool_bank(bank)
-        parts = [_draw_job(j) for j in jobs]
+        parts = [draw(j) for j in jobs]
     cat = lambda k: (np.concatenate([p[k] for p in parts]) if parts else np.zeros(0))
     words = cat("words").astype(np.uint32)
     road_len = cat("road_len").astype(np.int64)

@@ -23,6 +23,7 @@ from . import pipeline as P
 TILES = (4096, 8192)
 WG_SIZES = (256, 512)
 OCCUPANCIES = (1, 2, 3, 4)
+ONEPASS_OCCUPANCIES = (1, 2, 3)
 CHUNK_ROADS = 64
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "svt_tune.json")
 
@@ -31,10 +32,14 @@ EVENT_OCCUPANCIES = (2, 4)
 
 
 def candidates():
-    """Flat-tile shapes of the fused kernel, plus the one-event-per-workgroup schedule."""
-    flat = [L.make_tune(t, CHUNK_ROADS, wg, occ)
+    """The one-pass kernel at each resident grid size, the flat-tile shapes of the two-kernel
+    pass, and the one-event-per-workgroup schedule."""
+    onepass = [L.make_tune(0, 0, 0, occ, L.SVT_SCHEDULE_ONEPASS) for occ in ONEPASS_OCCUPANCIES]
+    flat = [L.make_tune(t, CHUNK_ROADS, wg, occ, L.SVT_SCHEDULE_TILES)
             for t in TILES for wg in WG_SIZES for occ in OCCUPANCIES]
-    return flat + [L.make_tune(4096, CHUNK_ROADS, 256, occ, 1) for occ in EVENT_OCCUPANCIES]
+    events = [L.make_tune(4096, CHUNK_ROADS, 256, occ, L.SVT_SCHEDULE_EVENTS)
+              for occ in EVENT_OCCUPANCIES]
+    return [L.svt_tune_resolve(t) for t in onepass + flat + events]
 
 
 def tune_tuple(t: L.svt_tune):
@@ -54,6 +59,7 @@ class TuneResult:
     tune: L.svt_tune
     ms_per_pass: float
     table: list  # (tile, chunk, wg, occ, schedule, ms)
+    statistic: str = ""
 
 
 def _digest(res: dict) -> str:
@@ -64,13 +70,15 @@ def _digest(res: dict) -> str:
 
 
 def autotune(words: torch.Tensor, bank: torch.Tensor, cfg: L.svt_config, n_roads: int,
-             n_combos: int, steps: int = 10, warmup: int = 2, cands=None,
-             cache_path: Optional[str] = DEFAULT_CACHE, use_cache: bool = True,
+             n_combos: int, samples: int = 30, per_sample: int = 5, warmup: int = 3,
+             cands=None, cache_path: Optional[str] = DEFAULT_CACHE, use_cache: bool = True,
              log=None) -> TuneResult:
     """Time every candidate on this batch (graph replays) and return the fastest.
 
-    ``words`` is a device int32 tensor of the batch's hit words.  Raises if two candidates
-    disagree on any output byte.
+    A candidate's time is the median over ``samples`` samples, each the mean of
+    ``per_sample`` back-to-back replays (host clock, synchronised around the sample), so one
+    stall of the runtime moves one sample and not the pick.  ``words`` is a device int32
+    tensor of the batch's hit words.  Raises if two candidates disagree on any output byte.
     """
     dev = torch.cuda.get_device_name()
     key = workload_key(words.numel(), n_roads, n_combos, dev)
@@ -81,7 +89,7 @@ def autotune(words: torch.Tensor, bank: torch.Tensor, cfg: L.svt_config, n_roads
             cached = None
         if cached:
             t = L.make_tune(*cached["tune"])
-            return TuneResult(t, cached["ms_per_pass"], cached.get("table", []))
+            return TuneResult(t, cached["ms_per_pass"], cached.get("table", []), "cached")
     table = []
     ref_digest = None
     best = None
@@ -92,11 +100,14 @@ def autotune(words: torch.Tensor, bank: torch.Tensor, cfg: L.svt_config, n_roads
         for _ in range(warmup):
             runner.run()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            runner.run()
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) / steps * 1e3
+        ts = []
+        for _ in range(samples):
+            t0 = time.perf_counter()
+            for _ in range(per_sample):
+                runner.run()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) / per_sample * 1e3)
+        ms = float(np.median(ts))
         d = _digest(runner.result())
         if ref_digest is None:
             ref_digest = d
@@ -110,7 +121,8 @@ def autotune(words: torch.Tensor, bank: torch.Tensor, cfg: L.svt_config, n_roads
         L.svt_release_graphs()
         del runner
         torch.cuda.empty_cache()
-    res = TuneResult(best[0], best[1], table)
+    res = TuneResult(best[0], best[1], table,
+                     f"median of {samples} samples of {per_sample} graph replays")
     if cache_path:
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)
         try:

@@ -86,3 +86,35 @@ def test_kept_only_capacity_reports_required_size(bank):
     torch.cuda.synchronize()
     assert runner.error() == (L.SVT_ERR_CAPACITY, 2)
     assert runner.sizes()["n_kept"] == ref["n_kept"]
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_kept_only_bad_input_reports_error_and_sizes(bank, graph):
+    """Kept-only passes over input the buffers or the bank cannot take: the pass reports the
+    error and the sizes the input needs, and reads nothing it was not given (the refit pass
+    runs after the error and must not touch the incomplete road table or a missing set)."""
+    s = synth.make_sample("c1", bank=bank)
+    ref = oracle.run(s.words, bank.f, bank.q, CFG)
+    w = P.words_tensor(s.words)
+    # too few road entries: capacity error with index 0 (roads), sizes still exact
+    small = P.BatchRunner(gpu_cfg(CFG), P.device_bank(bank.f, bank.q), len(s.words),
+                          ref["n_roads"] // 2, ref["n_combos"] + 4, kept_cap=ref["n_kept"] + 1,
+                          graph=graph, kept_only=True)
+    small.load(w).run()
+    torch.cuda.synchronize()
+    assert small.error() == (L.SVT_ERR_CAPACITY, 0)
+    sz = small.sizes()
+    assert (sz["n_roads"], sz["n_combos"]) == (ref["n_roads"], ref["n_combos"])
+    # a bank of 16 sets: road tags 16..255 have no constant set
+    cfg16 = oracle.make_config(chi2_cut=synth.DEFAULT_CHI2_CUT, n_sets=16)
+    bad = oracle.run(s.words, bank.f[:16], bank.q[:16], cfg16, raise_on_error=False)
+    assert bad["status"] == oracle.ERR_SET
+    r16 = P.BatchRunner(gpu_cfg(cfg16), P.device_bank(bank.f[:16], bank.q[:16]), len(s.words),
+                        ref["n_roads"], ref["n_combos"] + 4, kept_cap=ref["n_kept"] + 1,
+                        graph=graph, kept_only=True)
+    r16.load(w).run()
+    torch.cuda.synchronize()
+    assert r16.error() == (L.SVT_ERR_SET, bad["err_index"])
+    sz = r16.sizes()
+    assert (sz["n_roads"], sz["n_combos"]) == (ref["n_roads"], ref["n_combos"])
+    L.svt_release_graphs()

@@ -17,10 +17,13 @@ from paper_1312_0917_amd import synth
 pytestmark = pytest.mark.gpu
 
 CFG = oracle.make_config(chi2_cut=synth.DEFAULT_CHI2_CUT)
-TUNES = [L.make_tune(4096, 64, 256, 2), L.make_tune(8192, 64, 256, 3),
-         L.make_tune(4096, 64, 256, 4),  # a fourth workgroup per CU: a fourth priority slot
-         L.make_tune(4096, 64, 512, 1), L.make_tune(8192, 64, 512, 2),
-         L.make_tune(4096, 64, 256, 4, 1)]  # the last: one event per workgroup
+ONEPASS, EVENTS, TILES = L.SVT_SCHEDULE_ONEPASS, L.SVT_SCHEDULE_EVENTS, L.SVT_SCHEDULE_TILES
+TUNES = [L.make_tune(wgs_per_cu=1, schedule=ONEPASS), L.make_tune(wgs_per_cu=2, schedule=ONEPASS),
+         L.make_tune(wgs_per_cu=3, schedule=ONEPASS),
+         L.make_tune(4096, 64, 256, 2, TILES), L.make_tune(8192, 64, 256, 3, TILES),
+         L.make_tune(4096, 64, 256, 4, TILES),  # a fourth workgroup per CU: a fourth priority slot
+         L.make_tune(4096, 64, 512, 1, TILES), L.make_tune(8192, 64, 512, 2, TILES),
+         L.make_tune(4096, 64, 256, 4, EVENTS)]  # the last: one event per workgroup
 
 
 @pytest.fixture(scope="module")
@@ -41,10 +44,12 @@ def test_plain_path_matches_oracle(samples, bank, config):
 
 @pytest.mark.parametrize("config", ["c1", "c2", "c3"])
 @pytest.mark.parametrize("graph", [False, True])
-def test_batch_path_matches_oracle(samples, bank, config, graph):
+@pytest.mark.parametrize("schedule", [ONEPASS, TILES])
+def test_batch_path_matches_oracle(samples, bank, config, graph, schedule):
     s, ref = samples[config]
-    got, runner = run_batch(s.words, bank.f, bank.q, CFG, ref=ref, graph=graph)
-    compare(ref, got, BATCH_KEYS, f"batch {config} graph={graph}")
+    got, runner = run_batch(s.words, bank.f, bank.q, CFG, ref=ref, graph=graph,
+                            tune=L.make_tune(schedule=schedule))
+    compare(ref, got, BATCH_KEYS, f"batch {config} graph={graph} schedule={schedule}")
     if graph:  # a replay of the captured graph gives the same bytes
         runner.run()
         compare(ref, runner.result(), BATCH_KEYS, f"batch {config} replay")
