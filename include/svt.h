@@ -32,9 +32,10 @@
  *     svt_best structs; the caller allocates and owns all of them.  Structs themselves and
  *     svt_config / svt_tune are read from host memory during the call only.
  *   - The library allocates no device memory.  Scratch comes from the caller's workspace
- *     (d_work, work_bytes; size from the matching *_workspace function, 256-byte aligned).
- *     The only library-owned objects are the HIP graphs cached by svt_process_batch, freed by
- *     svt_release_graphs().
+ *     (d_work, work_bytes; size from the matching *_workspace function, 256-byte aligned), or
+ *     for svt_process_batch_static from a static array in the library's code object.  The
+ *     only other library-owned objects are the HIP graphs cached by svt_process_batch, freed
+ *     by svt_release_graphs().
  *   - Every call only enqueues work on `stream` and returns; nothing synchronises.
  *   - The return value reports host-side checks: SVT_OK, SVT_ERR_ARG (null pointer, negative
  *     size, bad configuration, misaligned output), SVT_ERR_HIP (a launch failed).  On an error
@@ -228,6 +229,32 @@ svt_status svt_process_batch(const svt_fconst *bank, const svt_config *cfg, cons
                              int64_t *kept, int64_t kept_cap, int64_t *d_n_roads,
                              int64_t *d_n_combos, int64_t *d_n_kept, uint64_t *d_err,
                              void *d_work, int64_t work_bytes, int32_t flags, hipStream_t stream);
+
+/* For callers that cannot allocate device memory -- code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc: svt_process_batch with the same arguments but no
+ * d_work / work_bytes.  Its workspace is one static array of SVT_STATIC_WORK_BYTES bytes per
+ * GPU, part of the library's code object and held until the process ends; the call allocates
+ * nothing.  Capacities whose workspace (svt_batch_workspace) exceeds that size return
+ * SVT_ERR_CAPACITY before anything is enqueued (svt_static_workspace_need reports both
+ * numbers); SVT_BATCH_GRAPH is SVT_ERR_ARG (instantiating a graph allocates -- capture the
+ * call in a graph of your own instead).  Every call on one GPU uses that GPU's array, and each
+ * pass clears what must start at zero: calls whose passes overlap on one GPU (other streams,
+ * other threads) race and give wrong results; serialise them.  Outputs and the device-side
+ * error word are exactly those of svt_process_batch. */
+#define SVT_STATIC_WORK_BYTES (32ll << 20)
+svt_status svt_process_batch_static(const svt_fconst *bank, const svt_config *cfg,
+                                    const svt_tune *tune, const uint32_t *words,
+                                    const int64_t *d_n_words, int64_t word_cap,
+                                    const svt_roads *roads, int64_t road_cap,
+                                    const svt_fitrec *rec, uint8_t *accept, int64_t combo_cap,
+                                    const svt_best *best, int64_t *kept, int64_t kept_cap,
+                                    int64_t *d_n_roads, int64_t *d_n_combos, int64_t *d_n_kept,
+                                    uint64_t *d_err, int32_t flags, hipStream_t stream);
+/* *need = the workspace these capacities take (svt_batch_workspace), *limit =
+ * SVT_STATIC_WORK_BYTES; SVT_OK if svt_process_batch_static accepts them, SVT_ERR_CAPACITY if
+ * they are too large, SVT_ERR_ARG for invalid capacities or tune. */
+svt_status svt_static_workspace_need(int64_t word_cap, int64_t road_cap, int64_t combo_cap,
+                                     const svt_tune *tune, int64_t *need, int64_t *limit);
 
 /* When both are non-NULL, svt_process_batch calls without SVT_BATCH_GRAPH record `start`
  * right before and `stop` right after the fused kernel, on the call's stream (for timing). */

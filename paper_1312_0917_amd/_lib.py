@@ -87,6 +87,10 @@ def load():
         "svt_process_batch": (_I32, [_P, S(svt_config), S(svt_tune), _P, _P, _I64, S(svt_roads),
                                      _I64, S(svt_fitrec), _P, _I64, S(svt_best), _P, _I64, _P,
                                      _P, _P, _P, _P, _I64, _I32, _P]),
+        "svt_process_batch_static": (_I32, [_P, S(svt_config), S(svt_tune), _P, _P, _I64,
+                                            S(svt_roads), _I64, S(svt_fitrec), _P, _I64,
+                                            S(svt_best), _P, _I64, _P, _P, _P, _P, _I32, _P]),
+        "svt_static_workspace_need": (_I32, [_I64, _I64, _I64, S(svt_tune), S(_I64), S(_I64)]),
         "svt_set_fused_timing_events": (None, [_P, _P]),
         "svt_release_graphs": (None, []),
         "svt_tune_resolve": (_I32, [S(svt_tune), S(svt_tune)]),
@@ -109,6 +113,7 @@ def exported_symbols():
     return ["svt_abi_version", "svt_status_name", "svt_error_decode", "svt_unpack_workspace",
             "svt_combine_workspace", "svt_select_workspace", "svt_batch_workspace", "svt_unpack",
             "svt_combine", "svt_fit", "svt_select", "svt_process_batch",
+            "svt_process_batch_static", "svt_static_workspace_need",
             "svt_set_fused_timing_events", "svt_release_graphs", "svt_tune_resolve",
             "svt_mapped_pointer", "svt_copy_async", "svt_event_record", "svt_event_done",
             "svt_gather_results"]
@@ -256,21 +261,34 @@ def svt_process_batch(bank, cfg, tune, words, d_n_words, word_cap, roads, road_c
                                     work.numel() * work.element_size(), flags, _stream(stream))
 
 
+def svt_static_workspace_need(word_cap, road_cap, combo_cap, tune=None):
+    """(status, workspace bytes these capacities take, bytes of the static workspace)."""
+    t = tune if tune is not None else make_tune()
+    need, limit = _I64(0), _I64(0)
+    st = load().svt_static_workspace_need(word_cap, road_cap, combo_cap, ctypes.byref(t),
+                                          ctypes.byref(need), ctypes.byref(limit))
+    return st, need.value, limit.value
+
+
 class PreparedBatch:
     """The argument list of svt_process_batch built once for a fixed set of buffers, so that a
     host loop pays one foreign call per batch (words, flags and stream may change per call)."""
 
     def __init__(self, bank, cfg, tune, d_n_words, word_cap, roads, road_cap, rec, accept,
                  combo_cap, best, kept, kept_cap, d_n_roads, d_n_combos, d_n_kept, d_err, work):
+        """``work`` None: call svt_process_batch_static (the library's static workspace)."""
         self._keep = (roads_struct(roads), fitrec_struct(rec), best_struct(best), cfg,
                       tune if tune is not None else make_tune())
         r, rc, b, c, t = self._keep
         self._head = (_ptr(bank), ctypes.byref(c), ctypes.byref(t))
         self._tail = (_ptr(d_n_words), word_cap, ctypes.byref(r), road_cap, ctypes.byref(rc),
                       _ptr(accept), combo_cap, ctypes.byref(b), _ptr(kept), kept_cap,
-                      _ptr(d_n_roads), _ptr(d_n_combos), _ptr(d_n_kept), _ptr(d_err), _ptr(work),
-                      work.numel() * work.element_size())
-        self._fn = load().svt_process_batch
+                      _ptr(d_n_roads), _ptr(d_n_combos), _ptr(d_n_kept), _ptr(d_err))
+        if work is None:
+            self._fn = load().svt_process_batch_static
+        else:
+            self._tail += (_ptr(work), work.numel() * work.element_size())
+            self._fn = load().svt_process_batch
 
     def __call__(self, words, flags, stream) -> int:
         return self._fn(*self._head, _ptr(words), *self._tail, flags, _stream(stream))

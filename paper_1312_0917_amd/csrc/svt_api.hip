@@ -459,14 +459,43 @@ static svt_status batch_sequence(const FusedLaunch &f, const BatchWs &w, int64_t
     return SVT_OK;
 }
 
-svt_status svt_process_batch(const svt_fconst *bank, const svt_config *cfg, const svt_tune *tune,
-                             const uint32_t *words, const int64_t *d_n_words, int64_t word_cap,
-                             const svt_roads *roads, int64_t road_cap, const svt_fitrec *rec,
-                             uint8_t *accept, int64_t combo_cap, const svt_best *best,
-                             int64_t *kept, int64_t kept_cap, int64_t *d_n_roads,
-                             int64_t *d_n_combos, int64_t *d_n_kept, uint64_t *d_err,
-                             void *d_work, int64_t work_bytes, int32_t flags,
-                             hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// ---- the workspace of svt_process_batch_static ----------------------------------------------
+// One array per GPU in this library's code object, held until the process ends.  In host code
+// its name is only the runtime's handle for it: the device address is taken once per device
+// with hipGetSymbolAddress and used everywhere instead.
+static __device__ __align__(256) char scratch[SVT_STATIC_WORK_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+svt_status static_workspace(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SVT_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SVT_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SVT_OK;
+}
+
+// work_bytes value that selects the static workspace (d_work is then ignored)
+constexpr int64_t kStaticWork = -2;
+
+// svt_process_batch on the caller's workspace, or on the static one (work_bytes == kStaticWork).
+svt_status process_batch(const svt_fconst *bank, const svt_config *cfg, const svt_tune *tune,
+                         const uint32_t *words, const int64_t *d_n_words, int64_t word_cap,
+                         const svt_roads *roads, int64_t road_cap, const svt_fitrec *rec,
+                         uint8_t *accept, int64_t combo_cap, const svt_best *best, int64_t *kept,
+                         int64_t kept_cap, int64_t *d_n_roads, int64_t *d_n_combos,
+                         int64_t *d_n_kept, uint64_t *d_err, void *d_work, int64_t work_bytes,
+                         int32_t flags, hipStream_t stream) {
     if (!config_ok(cfg) || !bank || !words || !d_n_words || !roads || !rec || !best ||
         !d_n_roads || !d_n_combos || !d_err || word_cap < 0 || word_cap > kMaxBatchWords ||
         road_cap < 0 || combo_cap < 0 ||
@@ -487,9 +516,17 @@ svt_status svt_process_batch(const svt_fconst *bank, const svt_config *cfg, cons
     if (!aligned(accept, 4)) return SVT_ERR_ARG;
     const svt_tune t = resolve_tune(tune);
     if (!fused_tune_supported(t)) return SVT_ERR_ARG;
-    if (!d_work || work_bytes < svt_batch_workspace(word_cap, road_cap, combo_cap, &t) ||
-        !aligned(d_work, kAlign))
+    if (work_bytes == kStaticWork) {  // svt_process_batch_static
+        if (flags & SVT_BATCH_GRAPH) return SVT_ERR_ARG;  // instantiating a graph allocates
+        if (svt_batch_workspace(word_cap, road_cap, combo_cap, &t) > SVT_STATIC_WORK_BYTES)
+            return SVT_ERR_CAPACITY;
+        const svt_status st = static_workspace(&d_work);
+        if (st != SVT_OK) return st;
+        work_bytes = SVT_STATIC_WORK_BYTES;
+    } else if (!d_work || work_bytes < svt_batch_workspace(word_cap, road_cap, combo_cap, &t) ||
+               !aligned(d_work, kAlign)) {
         return SVT_ERR_ARG;
+    }
     const int cus = num_cus();
     if (cus <= 0) return SVT_ERR_HIP;
 
@@ -566,6 +603,45 @@ svt_status svt_process_batch(const svt_fconst *bank, const svt_config *cfg, cons
     return SVT_OK;
 }
 
+
+}  // namespace
+
+extern "C" {
+
+svt_status svt_process_batch(const svt_fconst *bank, const svt_config *cfg, const svt_tune *tune,
+                             const uint32_t *words, const int64_t *d_n_words, int64_t word_cap,
+                             const svt_roads *roads, int64_t road_cap, const svt_fitrec *rec,
+                             uint8_t *accept, int64_t combo_cap, const svt_best *best,
+                             int64_t *kept, int64_t kept_cap, int64_t *d_n_roads,
+                             int64_t *d_n_combos, int64_t *d_n_kept, uint64_t *d_err,
+                             void *d_work, int64_t work_bytes, int32_t flags,
+                             hipStream_t stream) {
+    if (work_bytes < 0) return SVT_ERR_ARG;
+    return process_batch(bank, cfg, tune, words, d_n_words, word_cap, roads, road_cap, rec, accept,
+                         combo_cap, best, kept, kept_cap, d_n_roads, d_n_combos, d_n_kept, d_err,
+                         d_work, work_bytes, flags, stream);
+}
+
+svt_status svt_process_batch_static(const svt_fconst *bank, const svt_config *cfg,
+                                    const svt_tune *tune, const uint32_t *words,
+                                    const int64_t *d_n_words, int64_t word_cap,
+                                    const svt_roads *roads, int64_t road_cap,
+                                    const svt_fitrec *rec, uint8_t *accept, int64_t combo_cap,
+                                    const svt_best *best, int64_t *kept, int64_t kept_cap,
+                                    int64_t *d_n_roads, int64_t *d_n_combos, int64_t *d_n_kept,
+                                    uint64_t *d_err, int32_t flags, hipStream_t stream) {
+    return process_batch(bank, cfg, tune, words, d_n_words, word_cap, roads, road_cap, rec, accept,
+                         combo_cap, best, kept, kept_cap, d_n_roads, d_n_combos, d_n_kept, d_err,
+                         nullptr, kStaticWork, flags, stream);
+}
+
+svt_status svt_static_workspace_need(int64_t word_cap, int64_t road_cap, int64_t combo_cap,
+                                     const svt_tune *tune, int64_t *need, int64_t *limit) {
+    if (!need || !limit) return SVT_ERR_ARG;
+    *limit = SVT_STATIC_WORK_BYTES;
+    *need = svt_batch_workspace(word_cap, road_cap, combo_cap, tune);
+    return *need < 0 ? SVT_ERR_ARG : *need > *limit ? SVT_ERR_CAPACITY : SVT_OK;
+}
 void svt_release_graphs(void) {
     std::lock_guard<std::mutex> lock(g_graph_mu);
     for (auto &kv : graph_cache()) {

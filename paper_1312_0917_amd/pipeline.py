@@ -187,11 +187,13 @@ class BatchRunner:
     def __init__(self, cfg: L.svt_config, bank: torch.Tensor, word_cap: int, road_cap: int,
                  combo_cap: int, kept_cap: int = 0, tune: Optional[L.svt_tune] = None,
                  graph=True, with_c=True, device="cuda", stream=None, kept_only=False,
-                 n_words_ptr: Optional[int] = None):
+                 n_words_ptr: Optional[int] = None, static_workspace=False):
         """``kept_only``: no per-combination records; ``rec`` then holds the fit values of the
         accepted combinations, compacted in the order of the kept list (needs kept_cap > 0).
         ``n_words_ptr``: device address the kernels read the word count from (for instance
-        mapped host memory the caller writes), instead of the runner's own device word."""
+        mapped host memory the caller writes), instead of the runner's own device word.
+        ``static_workspace``: no workspace tensor; every pass goes through
+        svt_process_batch_static (the library's per-GPU static workspace, no graph)."""
         if kept_only and kept_cap <= 0:
             raise ValueError("kept-only mode needs a kept list (kept_cap > 0)")
         self.kept_only = kept_only
@@ -213,10 +215,20 @@ class BatchRunner:
         self.accept = torch.empty(max(combo_cap, 4) + 4, dtype=U8, device=d)
         self.best = _alloc_best(road_cap, d)
         self.kept = torch.empty(max(kept_cap, 1), dtype=I64, device=d) if kept_cap > 0 else None
-        nbytes = L.svt_batch_workspace(word_cap, road_cap, combo_cap, self.tune)
-        if nbytes < 0:
-            raise ValueError("unsupported tune / capacities")
-        self.work = _ws(nbytes, d)
+        if static_workspace:
+            if graph:
+                raise ValueError("the static workspace is for callers without graphs")
+            st, need, limit = L.svt_static_workspace_need(word_cap, road_cap, combo_cap,
+                                                          self.tune)
+            if st != L.SVT_OK:
+                raise ValueError(f"capacities need a {need}-byte workspace; the static one "
+                                 f"holds {limit} bytes")
+            self.work = None
+        else:
+            nbytes = L.svt_batch_workspace(word_cap, road_cap, combo_cap, self.tune)
+            if nbytes < 0:
+                raise ValueError("unsupported tune / capacities")
+            self.work = _ws(nbytes, d)
         d_n_words = self.d_n[0:1] if n_words_ptr is None else n_words_ptr
         self._call = L.PreparedBatch(self.bank, self.cfg, self.tune, d_n_words, self.word_cap,
                                      self.roads, self.road_cap, self.rec, self.accept,
@@ -253,7 +265,7 @@ class BatchRunner:
         src = self.words if words is None else words
         st = self._call(src, (L.SVT_BATCH_GRAPH if self.graph else 0) |
                         (L.SVT_BATCH_KEPT_ONLY if self.kept_only else 0), s)
-        L.check(st, "svt_process_batch")
+        L.check(st, "svt_process_batch" if self.work is not None else "svt_process_batch_static")
         return self
 
     def sizes(self):

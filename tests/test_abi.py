@@ -159,3 +159,35 @@ def test_tune_resolution_fills_defaults_and_rejects_unbuilt_shapes():
                 L.make_tune(wgs_per_cu=4, schedule=L.SVT_SCHEDULE_ONEPASS)]:
         with pytest.raises(L.SvtError):
             L.svt_tune_resolve(bad)
+
+
+def test_static_workspace_limit_and_host_rejections():
+    """svt_process_batch_static: capacities beyond its static workspace, a graph request and
+    invalid arguments are refused on the host, before any HIP call."""
+    lib = L.load()
+    st, need, limit = L.svt_static_workspace_need(4096, 512, 1 << 15)
+    assert st == L.SVT_OK and 0 < need <= limit
+    assert need == L.svt_batch_workspace(4096, 512, 1 << 15, L.make_tune())
+    st, need, limit = L.svt_static_workspace_need(1 << 30, 1 << 20, 1 << 30)
+    assert st == L.SVT_ERR_CAPACITY and need > limit
+    assert L.svt_static_workspace_need(-1, 0, 0)[0] == L.SVT_ERR_ARG
+    cfg, tune = L.make_config(), L.make_tune()
+    fake = 1 << 20
+    roads = L.svt_roads(*([fake] * 6))
+    rec = L.svt_fitrec(*([fake] * 4), None, None, None)
+    best = L.svt_best(*([fake] * 6))
+    args = [fake, ctypes.byref(cfg), ctypes.byref(tune), fake, fake, 4096, ctypes.byref(roads),
+            512, ctypes.byref(rec), fake, 1 << 15, ctypes.byref(best), None, 0, fake, fake, None,
+            fake, 0, None]
+    fn = lib.svt_process_batch_static
+    graph = list(args)
+    graph[18] = L.SVT_BATCH_GRAPH
+    assert fn(*graph) == L.SVT_ERR_ARG
+    big = list(args)
+    big[5] = 1 << 30
+    assert fn(*big) == L.SVT_ERR_CAPACITY
+    nobank = list(args)
+    nobank[0] = None
+    assert fn(*nobank) == L.SVT_ERR_ARG
+    # a negative workspace size stays an argument error on the workspace entry point
+    assert lib.svt_process_batch(*args[:18], fake, -2, 0, None) == L.SVT_ERR_ARG
