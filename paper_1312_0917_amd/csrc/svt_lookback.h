@@ -76,7 +76,7 @@ __device__ inline int64_t combos_of(uint32_t packed) {
 // words, or more than max_hits hits on a layer, and it has no combinations).  One wave; lane i
 // takes the block's words BW/64 * i .. BW/64 * (i + 1) - 1.
 template <int BW>
-__device__ __forceinline__ void block_aggregate(const LookbackCtx &a, int64_t p, uint64_t &agg0,
+__device__ void block_aggregate(const LookbackCtx &a, int64_t p, uint64_t &agg0,
                                 uint64_t &agg1) {
     constexpr int kPerLane = BW / kWaveSize;
     const int lane = lane_id();
@@ -134,16 +134,16 @@ __device__ inline void publish_aggregate(const LookbackCtx &a, int64_t b, uint64
 // Exclusive prefixes over blocks 0..b-1 of two status columns at once (col0[i], col1[i] =
 // column 0 and 1 of block i), for a block whose aggregates are already published
 // (publish_aggregate); publishes its inclusive prefixes once known.  Executed by one whole
-// wave; the results are valid in every lane.  One round reads NWIN * 64 predecessors
+// wave; the results are valid in every lane.  One round reads kLookWindows * 64 predecessors
 // of both columns (lane i of window k inspects block top - 64 k - i, so position 0 is the
 // nearest predecessor); each column sums its values up to its nearest block that already has
 // an inclusive value.  Values are opaque sums: counts packed in one word add field by field as
 // long as no field overflows.  A round that has waited a.timeout wall-clock ticks for
 // predecessors to publish computes their aggregates from the words instead (block_aggregate)
 // and goes on.
-template <int BW, int NWIN = kLookWindows>
-__device__ __forceinline__ void look_back2(const LookbackCtx &a, int64_t b, uint64_t agg0,
-                                           uint64_t agg1, uint64_t &ex0, uint64_t &ex1) {
+template <int BW>
+__device__ void look_back2(const LookbackCtx &a, int64_t b, uint64_t agg0, uint64_t agg1,
+                           uint64_t &ex0, uint64_t &ex1) {
     int64_t *col0 = a.status, *col1 = a.status + a.nb_cap;
     const int lane = lane_id();
     ex0 = 0;
@@ -152,22 +152,17 @@ __device__ __forceinline__ void look_back2(const LookbackCtx &a, int64_t b, uint
     bool done0 = false, done1 = false;
     int64_t top = b - 1;
     uint64_t wait_since = 0;  // start of this round's wait (0: not waiting)
-    // The first round reads one window: the nearest predecessors have usually published their
-    // inclusive prefixes already.  Windows not read count as empty aggregates (value 0).
-    int nwin = 1;
     while (!(done0 && done1)) {
-        uint64_t v0[NWIN], v1[NWIN];
+        uint64_t v0[kLookWindows], v1[kLookWindows];
 #pragma unroll
-        for (int k = 0; k < NWIN; ++k) {
+        for (int k = 0; k < kLookWindows; ++k) {
             const int64_t idx = top - 64 * k - lane;
-            const bool rd = k < nwin;
-            v0[k] = !rd ? kStAgg : (idx >= 0 && !done0) ? status_read(col0 + idx) : kStIncl;
-            v1[k] = !rd ? kStAgg : (idx >= 0 && !done1) ? status_read(col1 + idx) : kStIncl;
+            v0[k] = (idx >= 0 && !done0) ? status_read(col0 + idx) : kStIncl;
+            v1[k] = (idx >= 0 && !done1) ? status_read(col1 + idx) : kStIncl;
         }
-        const int span = 64 * nwin;
-        int f0 = span, f1 = span;  // nearest inclusive positions (span: none read)
+        int f0 = 64 * kLookWindows, f1 = 64 * kLookWindows;  // nearest inclusive positions
 #pragma unroll
-        for (int k = NWIN - 1; k >= 0; --k) {
+        for (int k = kLookWindows - 1; k >= 0; --k) {
             const uint64_t m0 = __ballot((v0[k] & kStMask) == kStIncl);
             const uint64_t m1 = __ballot((v1[k] & kStMask) == kStIncl);
             if (m0) f0 = 64 * k + __builtin_ctzll(m0);
@@ -175,7 +170,7 @@ __device__ __forceinline__ void look_back2(const LookbackCtx &a, int64_t b, uint
         }
         bool wait = false;
 #pragma unroll
-        for (int k = 0; k < NWIN; ++k) {
+        for (int k = 0; k < kLookWindows; ++k) {
             const int pos = 64 * k + lane;
             wait |= __ballot(((v0[k] & kStMask) == 0 && pos <= f0) ||
                              ((v1[k] & kStMask) == 0 && pos <= f1)) != 0;
@@ -192,7 +187,7 @@ __device__ __forceinline__ void look_back2(const LookbackCtx &a, int64_t b, uint
             // never overwrites what the block itself has published meanwhile (and what it
             // publishes later is the same aggregate, or its inclusive prefix).
             int need = (done0 ? -1 : f0) > (done1 ? -1 : f1) ? f0 : f1;  // farthest position
-            need = need < span ? need : span - 1;                         // of this round
+            need = need < 64 * kLookWindows ? need : 64 * kLookWindows - 1;  // of this round
             for (int64_t idx = top; idx >= 0 && top - idx <= need; --idx) {
                 const uint64_t s0 = status_read(col0 + idx), s1 = status_read(col1 + idx);
                 if ((s0 & kStMask) != 0 && (s1 & kStMask) != 0) continue;
@@ -209,17 +204,16 @@ __device__ __forceinline__ void look_back2(const LookbackCtx &a, int64_t b, uint
         wait_since = 0;
         uint64_t m0 = 0, m1 = 0;
 #pragma unroll
-        for (int k = 0; k < NWIN; ++k) {
+        for (int k = 0; k < kLookWindows; ++k) {
             const int pos = 64 * k + lane;
             if (!done0 && pos <= f0) m0 += v0[k] & ~kStMask;
             if (!done1 && pos <= f1) m1 += v1[k] & ~kStMask;
         }
         ex0 += wave_sum(m0);
         ex1 += wave_sum(m1);
-        done0 |= f0 < span;
-        done1 |= f1 < span;
-        top -= span;
-        nwin = NWIN;
+        done0 |= f0 < 64 * kLookWindows;
+        done1 |= f1 < 64 * kLookWindows;
+        top -= 64 * kLookWindows;
     }
     if (lane == 0) {
         status_publish(col0 + b, kStIncl | (ex0 + agg0));
