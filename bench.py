@@ -143,9 +143,35 @@ def measure_large(ls, passes, tune, bank):
 
     cut = synth.config_chi2_cut("c5")
     n_words, n_roads, n_combos = len(ls.words), ls.n_roads, ls.combos
-    runner = P.BatchRunner(L.make_config(chi2_cut=cut), P.device_bank(bank.f, bank.q), n_words,
-                           n_roads, n_combos, kept_cap=0, tune=tune, graph=True, with_c=False)
-    runner.load(P.words_tensor(ls.words))
+    gcfg, dbank = L.make_config(chi2_cut=cut), P.device_bank(bank.f, bank.q)
+    words = P.words_tensor(ls.words)
+    shapes = None
+    if tune is None:
+        # a short pick among the pre-pass + fused shapes (whole passes, 3 each after one)
+        shapes = {}
+        for tile, occ in ((4096, 3), (8192, 3), (4096, 4), (8192, 4)):
+            t = L.svt_tune_resolve(L.make_tune(tile, 64, 256, occ, L.SVT_SCHEDULE_TILES))
+            r = P.BatchRunner(gcfg, dbank, n_words, n_roads, n_combos, kept_cap=0, tune=t,
+                              graph=True, with_c=False)
+            r.load(words)
+            r.run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                r.run()
+            torch.cuda.synchronize()
+            shapes[f"{tile}x{occ}"] = round((time.perf_counter() - t0) / 3 * 1e3, 4)
+            assert r.error()[0] == 0, r.error()
+            L.svt_release_graphs()
+            del r
+        best = min(shapes, key=shapes.get)
+        tile, occ = (int(x) for x in best.split("x"))
+        tune = L.svt_tune_resolve(L.make_tune(tile, 64, 256, occ, L.SVT_SCHEDULE_TILES))
+        log(f"c5 launch shapes (ms per pass): {shapes}")
+    tune = L.svt_tune_for_batch(tune, n_words)
+    runner = P.BatchRunner(gcfg, dbank, n_words, n_roads, n_combos, kept_cap=0, tune=tune,
+                           graph=True, with_c=False)
+    runner.load(words)
     runner.run()
     torch.cuda.synchronize()
     sz = runner.sizes()
@@ -161,7 +187,7 @@ def measure_large(ls, passes, tune, bank):
     out = dict(workload=f"c5: {ls.n_events} events, {n_roads} roads, {n_words} hit words, "
                         f"{n_combos} combinations",
                value=n_combos / dt, unit="fitted combinations/s", ms_per_pass=round(dt * 1e3, 4),
-               passes=passes, tune=tune_dict(tune),
+               passes=passes, tune=tune_dict(tune), ms_per_pass_by_shape=shapes,
                roofline=roofline_of(tune, n_combos, n_words, n_roads, k_ms, dt * 1e3,
                                     recorded_traffic("c5", ls.n_events, tune)),
                int_ops=int_ops(n_combos, k_ms, tune))
@@ -188,7 +214,8 @@ def measure_uneven(sample, bank, log_fn):
     words = P.words_tensor(sample.words)
     res = T.autotune(words, P.device_bank(bank.f, bank.q), L.make_config(chi2_cut=cut), nr, nc,
                      cache_path=None, use_cache=False, log=log_fn)
-    default = [row for row in res.table if row[:5] == T.tune_tuple(L.svt_tune_resolve(None))]
+    default = [row for row in res.table
+               if row[:5] == T.tune_tuple(L.svt_tune_for_batch(None, len(sample.words)))]
     by_sched = {}
     for row in res.table:
         by_sched[row[4]] = min(by_sched.get(row[4], 1e30), row[5])
@@ -225,16 +252,25 @@ def measure_serving(sample, bank, warmup_events, rate_hz, n_slots, max_events, t
     dbank = P.device_bank(bank.f, bank.q)
     warm = serve.EventStream(sample.words, sample.event_word_begin, np.zeros(n_events))
     out = {}
-    for io in ("mapped", "copy"):
+    # (io, timing, graph, launch sized to the batch)
+    runs = {"mapped": ("mapped", False, True, True), "mapped_timed": ("mapped", True, True, True),
+            "mapped_direct": ("mapped", False, False, True),
+            "mapped_slot_grid": ("mapped", False, True, False),
+            "copy": ("copy", False, True, True)}
+    for name, (io, timing, graph, sized) in runs.items():
         slots = [serve.GpuSlot(cfg, dbank, word_cap, word_cap // 5 + 1, combo_cap, tune=tune,
-                               io=io) for _ in range(n_slots)]
-        # capture each slot's graph before the clock starts
+                               io=io, timing=timing, graph=graph, size_to_batch=sized)
+                 for _ in range(n_slots)]
+        # capture every slot's graphs before the clock starts
         for sl in slots:
-            sl.launch(warm.slice(0, 1), 0, 1)
-            sl._wait()
-            sl.collect()
+            sl.warm(warm.slice(0, 1))
         stats, _ = serve.serve(st, slots, max_events=max_events)
-        out[io] = stats.summary(warmup_events)
+        out[name] = stats.summary(warmup_events)
+        caps = slots[0].launch_caps()
+        out[name]["launch"] = dict(
+            graph=graph, word_caps=[caps[0], caps[-1]],
+            schedule_smallest=L.svt_tune_for_batch(tune, caps[0]).schedule,
+            schedule_largest=L.svt_tune_for_batch(tune, caps[-1]).schedule)
         L.svt_release_graphs()
         del slots
         torch.cuda.empty_cache()
@@ -244,9 +280,23 @@ def measure_serving(sample, bank, warmup_events, rate_hz, n_slots, max_events, t
                          f"Poisson stream at {rate_hz / 1e3:.0f} kHz, {mean_w:.0f} words and "
                          f"{mean_c:.0f} combinations per event on average",
                 slots=n_slots, max_events_per_batch=max_events,
+                slot_word_cap=word_cap,
                 batched_io="words read and results written in place in page-locked host "
                            "memory (no copy calls); batched_copy: H2D and two-step D2H copies",
-                batched=out["mapped"], batched_copy=out["copy"], plain=plain)
+                batched=out["mapped"],
+                launch_shapes="batched: graphs for power-of-two word capacities from 4096 up, "
+                              "each batch launched for the smallest that holds it (small "
+                              "capacities run the one-pass kernel); batched_direct: the same "
+                              "without graphs; batched_slot_grid: every batch launched for the "
+                              "slot's whole capacity",
+                batched_direct=out["mapped_direct"], batched_slot_grid=out["mapped_slot_grid"],
+                batched_breakdown=dict(
+                    note="the same stream and slots with a timed HIP event before each batch "
+                         "(its overhead included); per event: queue = arrival to launch call, "
+                         "enqueue = launch call, device = first to last operation of the batch "
+                         "on its stream, visible = end of the launch call to the host seeing "
+                         "the results, less the device time", **out["mapped_timed"]),
+                batched_copy=out["copy"], plain=plain)
 
 
 def measure_transfer(sample, bank, tune, reps):
@@ -476,8 +526,8 @@ def main():
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--occ", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=-1,
-                    help="launch schedule (0 two-kernel pass, 1 event per workgroup, 2 one "
-                         "pass); default: the built-in or autotuned one")
+                    help="launch schedule (0 built-in default, 1 event per workgroup, 2 one "
+                         "pass, 3 pre-pass + fused tiles); default: the built-in or autotuned one")
     ap.add_argument("--large-events", type=int, default=10000,
                     help="events of the max-scale run (10000 x 2048 roads); 0 skips it")
     ap.add_argument("--large-passes", type=int, default=5)
@@ -580,6 +630,8 @@ def main():
         tune = res.tune
         tuned = dict(candidates=len(res.table), best_ms_per_pass=round(res.ms_per_pass, 5),
                      statistic=res.statistic)
+    # the schedule the library runs for this batch (a zero schedule is chosen per capacity)
+    tune = L.svt_tune_for_batch(tune, n_words)
 
     # ---- batched path: resident buffers, graph replay -------------------------------------
     runner = P.BatchRunner(gcfg, dbank, n_words, n_roads, n_combos, kept_cap=0, tune=tune,
@@ -725,8 +777,7 @@ def main():
         L.svt_release_graphs()
         del runner
         torch.cuda.empty_cache()
-        large = measure_large(large_s, args.large_passes,
-                              tune if explicit_tune else default_tune, bank)
+        large = measure_large(large_s, args.large_passes, tune if explicit_tune else None, bank)
 
     out = dict(
         metric=METRIC, value=value, unit="fitted combinations/s", n_gpus=1, steps=K, warmup=W,

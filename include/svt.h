@@ -130,9 +130,13 @@ typedef struct svt_tune {
     int32_t tile_combos;  /* two-kernel schedule: combinations per work tile, 4096 or 8192 */
     int32_t chunk_roads;  /* two-kernel schedule: roads staged in LDS at once, 64 */
     int32_t wg_size;      /* two-kernel schedule: 256 or 512 (one loader wave, the rest fit) */
-    int32_t wgs_per_cu;   /* persistent workgroups per compute unit, 1..8 */
-    int32_t schedule;     /* SVT_SCHEDULE_*; 0 picks the built-in one (one pass).  The fields a
-                             schedule does not use only have to be valid values. */
+    int32_t wgs_per_cu;   /* persistent workgroups per compute unit, 1..8 (one pass: 1..3);
+                             the two-kernel schedule launches no more workgroups than
+                             combo_cap has tiles */
+    int32_t schedule;     /* SVT_SCHEDULE_*; 0 chooses per call from word_cap: the one-pass
+                             kernel up to 2^19 words, the two-kernel schedule above (0 must
+                             then suit both: wgs_per_cu 1..3).  The fields a schedule does
+                             not use only have to be valid values. */
 } svt_tune;
 /* One persistent kernel that unpacks, combines, fits and selects units of 1024 words, each
  * workgroup holding its unit's roads, pair tables and best tracks in LDS (the loop nest of
@@ -301,6 +305,9 @@ void svt_release_graphs(void);
  * take the built-in defaults).  Returns SVT_ERR_ARG when `out` is NULL or the resolved set is
  * not one the fused kernel is built for, SVT_OK otherwise.  Host memory only. */
 svt_status svt_tune_resolve(const svt_tune *tune, svt_tune *out);
+/* The launch parameters svt_process_batch uses for `tune` at word capacity word_cap: as
+ * svt_tune_resolve, with a zero schedule replaced by the one chosen for that capacity. */
+svt_status svt_tune_for_batch(const svt_tune *tune, int64_t word_cap, svt_tune *out);
 
 /* Turn an error word into a status (SVT_OK when none) and its index (-1 when none). */
 svt_status svt_error_decode(uint64_t err, int64_t *index);

@@ -20,7 +20,7 @@ SVT_NO_ERROR = (1 << 64) - 1
 SVT_BATCH_GRAPH = 1
 SVT_BATCH_KEPT_ONLY = 2
 SVT_SCHEDULE_EVENTS = 1   # one event per workgroup (ablation)
-SVT_SCHEDULE_ONEPASS = 2  # the built-in: one persistent kernel per pass (plus a reset)
+SVT_SCHEDULE_ONEPASS = 2  # one persistent kernel per pass (plus a reset)
 SVT_SCHEDULE_TILES = 3    # pre-pass, persistent kernel over flat tiles, finalize
 SVT_COPY_H2D = 1
 SVT_COPY_D2H = 2
@@ -94,6 +94,7 @@ def load():
         "svt_set_fused_timing_events": (None, [_P, _P]),
         "svt_release_graphs": (None, []),
         "svt_tune_resolve": (_I32, [S(svt_tune), S(svt_tune)]),
+        "svt_tune_for_batch": (_I32, [S(svt_tune), _I64, S(svt_tune)]),
         "svt_mapped_pointer": (_I32, [_P, S(_P)]),
         "svt_copy_async": (_I32, [_P, _P, _I64, _I32, _P]),
         "svt_event_record": (_I32, [_P, _P]),
@@ -115,6 +116,7 @@ def exported_symbols():
             "svt_combine", "svt_fit", "svt_select", "svt_process_batch",
             "svt_process_batch_static", "svt_static_workspace_need",
             "svt_set_fused_timing_events", "svt_release_graphs", "svt_tune_resolve",
+            "svt_tune_for_batch",
             "svt_mapped_pointer", "svt_copy_async", "svt_event_record", "svt_event_done",
             "svt_gather_results"]
 
@@ -150,6 +152,15 @@ def svt_tune_resolve(tune=None) -> svt_tune:
     out = svt_tune()
     check(load().svt_tune_resolve(ctypes.byref(tune) if tune is not None else None,
                                   ctypes.byref(out)), "svt_tune_resolve")
+    return out
+
+
+def svt_tune_for_batch(tune, word_cap) -> svt_tune:
+    """Launch parameters svt_process_batch uses for ``tune`` at word capacity ``word_cap``
+    (a zero schedule becomes the one chosen for that capacity)."""
+    out = svt_tune()
+    check(load().svt_tune_for_batch(ctypes.byref(tune) if tune is not None else None, word_cap,
+                                    ctypes.byref(out)), "svt_tune_for_batch")
     return out
 
 

@@ -70,6 +70,7 @@ struct BatchWs {
     int64_t *kb;
     int64_t kbn;
     int16_t *coords;
+    int64_t *nw_copy;   // the batch's word count, copied to device memory by the reset
 };
 BatchWs carve_batch(Carver &c, int64_t word_cap, int64_t road_cap, int64_t combo_cap,
                     int64_t tile) {
@@ -88,11 +89,20 @@ BatchWs carve_batch(Carver &c, int64_t word_cap, int64_t road_cap, int64_t combo
     w.kbn = ceil_div(combo_cap > 0 ? combo_cap : 1, kKeptBlock);
     w.kb = c.take<int64_t>(w.kbn);
     w.coords = c.take<int16_t>(word_cap + 16);  // slack for 16-byte reads of the last span
+    w.nw_copy = c.take<int64_t>(1);
     return w;
 }
 
-svt_tune resolve_tune(const svt_tune *t) {
-    svt_tune r{4096, 64, 256, 3, SVT_SCHEDULE_ONEPASS};
+// Batches of at most this many words (capacity) run the one-pass kernel by default, larger ones
+// the pre-pass and fused kernels: per-unit latency dominates the one-pass kernel once every
+// workgroup has several units of small roads (on 3000 events of 64 roads the two tie at the
+// default tile, and the pre-pass path leads with 8192-combination tiles).
+constexpr int64_t kOnepassDefaultWords = 1 << 19;
+
+// Launch parameters for `t` (zero fields take the defaults).  A zero schedule stays zero when
+// no capacity is given (word_cap < 0), and is chosen from the capacity otherwise.
+svt_tune resolve_tune(const svt_tune *t, int64_t word_cap = -1) {
+    svt_tune r{4096, 64, 256, 3, 0};
     if (t) {
         if (t->tile_combos) r.tile_combos = t->tile_combos;
         if (t->chunk_roads) r.chunk_roads = t->chunk_roads;
@@ -100,6 +110,8 @@ svt_tune resolve_tune(const svt_tune *t) {
         if (t->wgs_per_cu) r.wgs_per_cu = t->wgs_per_cu;
         if (t->schedule) r.schedule = t->schedule;
     }
+    if (r.schedule == 0 && word_cap >= 0)
+        r.schedule = word_cap <= kOnepassDefaultWords ? SVT_SCHEDULE_ONEPASS : SVT_SCHEDULE_TILES;
     return r;
 }
 
@@ -195,6 +207,12 @@ svt_status svt_tune_resolve(const svt_tune *tune, svt_tune *out) {
     return fused_tune_supported(*out) ? SVT_OK : SVT_ERR_ARG;
 }
 
+svt_status svt_tune_for_batch(const svt_tune *tune, int64_t word_cap, svt_tune *out) {
+    if (!out || word_cap < 0) return SVT_ERR_ARG;
+    *out = resolve_tune(tune, word_cap);
+    return fused_tune_supported(*out) ? SVT_OK : SVT_ERR_ARG;
+}
+
 const char *svt_status_name(svt_status s) {
     switch (s) {
         case SVT_OK: return "SVT_OK";
@@ -244,7 +262,7 @@ int64_t svt_select_workspace(int64_t n_combos) {
 int64_t svt_batch_workspace(int64_t word_cap, int64_t road_cap, int64_t combo_cap,
                             const svt_tune *tune) {
     if (word_cap < 0 || word_cap > kMaxBatchWords || road_cap < 0 || combo_cap < 0) return -1;
-    const svt_tune t = resolve_tune(tune);
+    const svt_tune t = resolve_tune(tune, word_cap);
     if (!fused_tune_supported(t)) return -1;
     Carver c{nullptr};
     carve_batch(c, word_cap, road_cap, combo_cap, t.tile_combos);
@@ -355,6 +373,8 @@ static svt_status batch_sequence(const FusedLaunch &f, const BatchWs &w, int64_t
                                  int64_t kept_cap, int64_t *d_n_kept, bool timing,
                                  hipStream_t stream) {
     const Sizes nw{0, f.d_n_words, word_cap};
+    // after the reset the kernels read the word count from its copy in device memory
+    const Sizes nw_dev{0, w.nw_copy, word_cap};
     const Sizes nr{0, f.d_n_roads, road_cap};
     const Sizes nc{0, f.d_n_combos, combo_cap};
     PrepassLaunch p{};
@@ -382,13 +402,13 @@ static svt_status batch_sequence(const FusedLaunch &f, const BatchWs &w, int64_t
     if (f.tune.schedule == SVT_SCHEDULE_ONEPASS) {
         // reset, the one-pass kernel, and with a kept list its scan and compaction
         p.nb_cap = w.nb;
-        SVT_TRY(launch_batch_reset(p, kOnepassUnitWords, d_n_kept, d_n_kept ? w.kb : nullptr,
+        SVT_TRY(launch_batch_reset(p, w.nw_copy, d_n_kept, d_n_kept ? w.kb : nullptr,
                                    d_n_kept ? w.kbn : 0, stream));
         OnepassLaunch o{};
         o.bank = f.bank;
         o.cfg = f.cfg;
         o.words = f.words;
-        o.nw = nw;
+        o.nw = nw_dev;
         o.roads = f.roads;
         o.road_cap = road_cap;
         o.rec = f.rec;
@@ -426,8 +446,9 @@ static svt_status batch_sequence(const FusedLaunch &f, const BatchWs &w, int64_t
     }
     // (the kept-list block counts are cleared with the rest: the fused kernel adds to them)
     p.nb_cap = ceil_div(word_cap > 0 ? word_cap : 1, kPrepassBlockWords);
-    SVT_TRY(launch_batch_reset(p, kPrepassBlockWords, d_n_kept, d_n_kept ? w.kb : nullptr,
+    SVT_TRY(launch_batch_reset(p, w.nw_copy, d_n_kept, d_n_kept ? w.kb : nullptr,
                                d_n_kept ? w.kbn : 0, stream));
+    p.nw = nw_dev;
     SVT_TRY(launch_prepass(p, stream));
     if (timing) SVT_TRY(hipEventRecord(g_ev_start, stream));
     if (f.tune.schedule == SVT_SCHEDULE_EVENTS)
@@ -514,7 +535,7 @@ svt_status process_batch(const svt_fconst *bank, const svt_config *cfg, const sv
     for (const void *p : a16)
         if (p && !aligned(p, 16)) return SVT_ERR_ARG;
     if (!aligned(accept, 4)) return SVT_ERR_ARG;
-    const svt_tune t = resolve_tune(tune);
+    const svt_tune t = resolve_tune(tune, word_cap);
     if (!fused_tune_supported(t)) return SVT_ERR_ARG;
     if (work_bytes == kStaticWork) {  // svt_process_batch_static
         if (flags & SVT_BATCH_GRAPH) return SVT_ERR_ARG;  // instantiating a graph allocates

@@ -259,13 +259,13 @@ struct PrepassLaunch {
 // Clears the error word, both tickets, *d_n_kept (nullable), the status words in use (one pair
 // per block_words words of the batch) and zero[0 .. n_zero) (the kept-list block counts;
 // nullable).
-hipError_t launch_batch_reset(const PrepassLaunch &p, int64_t block_words, int64_t *d_n_kept,
+hipError_t launch_batch_reset(const PrepassLaunch &p, int64_t *nw_copy, int64_t *d_n_kept,
                               int64_t *zero, int64_t n_zero, hipStream_t s);
 hipError_t launch_prepass(const PrepassLaunch &p, hipStream_t s);
 
 // The whole batched pass in one persistent kernel (unpack, combine, fit, select; road table,
-// records and best tracks written from LDS).  Needs the reset of launch_batch_reset with
-// block_words = kOnepassUnitWords first.
+// records and best tracks written from LDS).  Needs the reset of launch_batch_reset (with
+// nb_cap status words for units of kOnepassUnitWords) first.
 struct OnepassLaunch {
     const svt_fconst *bank;
     svt_config cfg;

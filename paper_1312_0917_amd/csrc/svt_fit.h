@@ -117,19 +117,71 @@ struct Fit {
     int64_t chi2;
 };
 
+// Arithmetic forms of the fit, all exact (same values as the int64 definition):
+//   kFitSplit  q = qh * 2^s + ql, ql seeds each row, qh is added after the shift;
+//   kFitFold   the same with ql carried in the layer-4 pair (shift <= 15, see fit_xyz);
+//   kFitNarrow the whole offset seeds each row and the chi-square is summed in 32 bits.  Valid
+//              for a constant set whose bounds narrow_ok() accepts: every row's sum stays in
+//              int32 for any int13 coordinates, and every chi-square component has |c| < 2^15,
+//              so c^2 < 2^30 and the sum of three is below 2^32.
+constexpr int kFitSplit = 0;
+constexpr int kFitFold = 1;
+constexpr int kFitNarrow = 2;
+
+// Whether a constant set allows kFitNarrow: with |x_l| <= 2^12 the row sum S_j + q_j lies in
+// [-B_j, B_j] for B_j = 2^12 * sum_l |f_jl| + |q_j|; int32 needs B_j < 2^31, and the shifted
+// value floor((S_j + q_j) / 2^s) then has magnitude at most (B_j >> s) + 1, which must stay
+// below 2^15 for the chi-square rows (j = 3..5).  f holds the set's 30 constants row-major.
+__device__ __forceinline__ bool narrow_ok(const int32_t *f, const int32_t *q, int32_t shift) {
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        int64_t sf = 0;
+#pragma unroll
+        for (int l = 0; l < 5; ++l) sf += f[5 * j + l] < 0 ? -f[5 * j + l] : f[5 * j + l];
+        const int64_t b = (sf << 12) + (q[j] < 0 ? -static_cast<int64_t>(q[j]) : q[j]);
+        ok &= b < (1ll << 31);
+        if (j >= 3) ok &= (b >> shift) + 1 < (1ll << 15);
+    }
+    return ok;
+}
+
+// a * b + c on the full-rate 24-bit signed multiplier (low 32 bits of the result)
+__device__ __forceinline__ int32_t mad_i24(int32_t a, int32_t b, int32_t c) {
+    int32_t r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 // The six rows of one combination from its three coordinate pairs.  Each sum
 //     ql_j + f_j0 x0 + f_j1 x1 + f_j2 x2 + f_j3 x3 + f_j4 x4
 // is three packed 16-bit dot products; |sum| < 2^30 + 5 * 2^27 < 2^31, so int32 is exact.
 // With FOLD (shift <= 15, so 0 <= ql < 2^15) ql rides in the layer-4 pair, (f_j4, ql_j) .
 // (x4, 1), and every row starts from zero instead of from a copy of ql.
-template <bool FOLD, typename CT>
+// With kFitNarrow the constants hold the whole offset in ql and (f_j4, 0) in F4, and each row
+// is three dot products and a shift.
+template <int MODE, typename CT>
 __device__ __forceinline__ Fit fit_xyz(const CT &c, int32_t x01, int32_t x23, int32_t x4,
                                        int32_t shift) {
     Fit f;
+    if constexpr (MODE == kFitNarrow) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            int32_t acc = dot2(c.F01[j], x01, c.ql[j]);
+            acc = dot2(c.F23[j], x23, acc);
+            acc = dot2(c.F4[j], x4, acc);
+            f.v[j] = acc >> shift;
+        }
+        // each square < 2^30: the 32-bit sum wraps past 2^31 but stays below 2^32
+        const int32_t s2 = mad_i24(f.v[3], f.v[3], mad_i24(f.v[4], f.v[4], 0));
+        f.chi2 = static_cast<int64_t>(
+            static_cast<uint32_t>(mad_i24(f.v[5], f.v[5], s2)));
+        return f;
+    }
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
         int32_t acc;
-        if constexpr (FOLD) {
+        if constexpr (MODE == kFitFold) {
             acc = dot2_zero(c.F4[j], x4);
             acc = dot2(c.F01[j], x01, acc);
             acc = dot2(c.F23[j], x23, acc);
@@ -147,7 +199,7 @@ __device__ __forceinline__ Fit fit_xyz(const CT &c, int32_t x01, int32_t x23, in
 
 // Fit combination k of a road.  k = (i01 * n23 + i23) * n4 + h4, where i01 = h0 * n1 + h1
 // and i23 = h2 * n3 + h3 index the coordinate-pair tables.
-template <bool FOLD, typename CT>
+template <int MODE, typename CT>
 __device__ __forceinline__ Fit fit_combo(const RoadMeta &m, const CT &c, uint32_t k,
                                          const int32_t *XT, int32_t shift) {
     const uint32_t n4 = m.n4(), n23 = m.n23();
@@ -155,7 +207,7 @@ __device__ __forceinline__ Fit fit_combo(const RoadMeta &m, const CT &c, uint32_
     const uint32_t h4 = k - mul_u24(q4, n4);
     const uint32_t i01 = div_small(q4, m.w23);
     const uint32_t i23 = q4 - mul_u24(i01, n23);
-    return fit_xyz<FOLD, CT>(c, XT[m.b01() + static_cast<int32_t>(i01)],
+    return fit_xyz<MODE, CT>(c, XT[m.b01() + static_cast<int32_t>(i01)],
                          XT[m.b23() + static_cast<int32_t>(i23)],
                          XT[m.b4() + static_cast<int32_t>(h4)], shift);
 }
@@ -163,11 +215,38 @@ __device__ __forceinline__ Fit fit_combo(const RoadMeta &m, const CT &c, uint32_
 // Four consecutive combinations k0, k0 + 1, k0 + 2, k0 + 3 of one road (k0 may lie up to 3
 // outside [0, C); those slots get a harmless dummy).  The table indices of the first are
 // divided out once and the others stepped from it, carrying h4 -> i23 -> i01.
-template <bool FOLD, typename CT>
+//
+// From a start inside the road (k0 >= 0) the steps need no bounds: past the road's last
+// combination h4 and i23 keep wrapping and i01 passes n01 by at most 2 (when n23 * n4 = 1),
+// so a read lands in the road's own (h2, h3) or layer-4 table or one entry past the road's
+// tables -- still LDS of the staging buffer; such slots are not written.
+template <int MODE, typename CT>
 __device__ __forceinline__ void fit4(const RoadMeta &m, const CT &c, int32_t k0,
                                      const int32_t *XT, int32_t shift, Fit *out) {
     const int32_t C = m.C();
     const uint32_t n4 = m.n4(), n23 = m.n23();
+    if (MODE == kFitNarrow && k0 >= 0) {
+        const uint32_t k = static_cast<uint32_t>(k0);
+        const uint32_t q4 = div_small(k, m.w4);
+        uint32_t h4 = k - mul_u24(q4, n4);
+        uint32_t i01 = div_small(q4, m.w23);
+        uint32_t i23 = q4 - mul_u24(i01, n23);
+        const int32_t *t01 = XT + m.b01(), *t23 = XT + m.b23(), *t4 = XT + m.b4();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            out[e] = fit_xyz<MODE, CT>(c, t01[i01], t23[i23], t4[h4], shift);
+            if (e < 3) {
+                ++h4;
+                const bool w4 = h4 == n4;
+                h4 = w4 ? 0u : h4;
+                i23 += w4 ? 1u : 0u;
+                const bool w23 = i23 == n23;
+                i23 = w23 ? 0u : i23;
+                i01 += w23 ? 1u : 0u;
+            }
+        }
+        return;
+    }
     const uint32_t k = static_cast<uint32_t>(k0 < 0 ? 0 : (k0 > C - 1 ? C - 1 : k0));
     const uint32_t q4 = div_small(k, m.w4);
     uint32_t h4 = k - mul_u24(q4, n4);
@@ -175,7 +254,7 @@ __device__ __forceinline__ void fit4(const RoadMeta &m, const CT &c, int32_t k0,
     uint32_t i23 = q4 - mul_u24(i01, n23);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        out[e] = fit_xyz<FOLD, CT>(c, XT[m.b01() + static_cast<int32_t>(i01)],
+        out[e] = fit_xyz<MODE, CT>(c, XT[m.b01() + static_cast<int32_t>(i01)],
                                XT[m.b23() + static_cast<int32_t>(i23)],
                                XT[m.b4() + static_cast<int32_t>(h4)], shift);
         if (e < 3 && k0 + e >= 0 && k0 + e + 1 < C) {  // step to k0 + e + 1

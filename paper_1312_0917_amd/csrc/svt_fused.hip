@@ -20,6 +20,8 @@
 // counts and the kept-list block counts are reduced with global atomics from the (rare)
 // accepted combinations, which needs no synchronisation between compute waves; a small pass
 // after the kernel turns the per-road keys into best tracks.
+#include <algorithm>
+
 #include "svt_fit.h"
 
 namespace svt {
@@ -72,6 +74,7 @@ struct Stage {
     int64_t tile_start;
     int64_t r_first;                       // global index of staged road 0
     int32_t nr, cs, ce, g_lo, g_hi, nx, done;
+    int32_t narrow;                        // every staged road allows kFitNarrow (its rc too)
     int32_t work[2];                       // next unclaimed group / listed group (LDS atomics)
 };
 
@@ -215,18 +218,28 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
             m.b4c = static_cast<uint32_t>(to + n0 * n1 + n2 * n3) | (static_cast<uint32_t>(C) << 16);
             S.meta[lane] = m;
             S.rb[lane] = rb;
-            const int32_t qv[6] = {static_cast<int32_t>(qw[0].x), static_cast<int32_t>(qw[0].y),
-                                   static_cast<int32_t>(qw[1].x), static_cast<int32_t>(qw[1].y),
-                                   static_cast<int32_t>(qw[2].x), static_cast<int32_t>(qw[2].y)};
+        }
+        // the narrow form for the whole chunk when every staged road's constants allow it
+        int32_t qv[6], fv[30];
+#pragma unroll
+        for (int i = 0; i < 30; ++i) fv[i] = f_el(fw, i);
+        qv[0] = static_cast<int32_t>(qw[0].x);
+        qv[1] = static_cast<int32_t>(qw[0].y);
+        qv[2] = static_cast<int32_t>(qw[1].x);
+        qv[3] = static_cast<int32_t>(qw[1].y);
+        qv[4] = static_cast<int32_t>(qw[2].x);
+        qv[5] = static_cast<int32_t>(qw[2].y);
+        const bool narrow = __ballot(fits && !narrow_ok(fv, qv, a.shift)) == 0;
+        if (fits) {
             RoadConst rc;
 #pragma unroll
             for (int j = 0; j < 6; ++j) {
-                rc.F01[j] = pack16(f_el(fw, 5 * j + 0), f_el(fw, 5 * j + 1));
-                rc.F23[j] = pack16(f_el(fw, 5 * j + 2), f_el(fw, 5 * j + 3));
-                rc.F4[j] = pack16(f_el(fw, 5 * j + 4),
-                                  a.fold ? static_cast<int32_t>(static_cast<uint32_t>(qv[j]) & qlmask) : 0);
-                rc.qh[j] = qv[j] >> a.shift;
-                rc.ql[j] = static_cast<int32_t>(static_cast<uint32_t>(qv[j]) & qlmask);
+                rc.F01[j] = pack16(fv[5 * j + 0], fv[5 * j + 1]);
+                rc.F23[j] = pack16(fv[5 * j + 2], fv[5 * j + 3]);
+                const int32_t ql = static_cast<int32_t>(static_cast<uint32_t>(qv[j]) & qlmask);
+                rc.F4[j] = pack16(fv[5 * j + 4], (a.fold && !narrow) ? ql : 0);
+                rc.qh[j] = narrow ? 0 : qv[j] >> a.shift;
+                rc.ql[j] = narrow ? qv[j] : ql;
             }
 #pragma unroll
             for (int j = 0; j < 6; ++j) rc.pad[j] = 0;
@@ -297,6 +310,7 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
             S.g_lo = g_lo;
             S.g_hi = g_hi;
             S.done = 0;
+            S.narrow = narrow ? 1 : 0;
             S.work[0] = 0;
             S.work[1] = 0;
         }
@@ -315,7 +329,7 @@ __device__ __forceinline__ int32_t claim64(int32_t *counter) {
 
 // A group whose valid slots all lie in staged road ri: four fits with one road's constants
 // (slots outside `slots` compute a harmless dummy, k = 0, and are not written).
-template <bool FOLD, int REC>
+template <int MODE, int REC>
 __device__ __forceinline__ void fit_group(const FArgs &a, const Stage &S, int ri, int32_t rel0,
                                           uint32_t slots, int64_t tile_start, int64_t r_first) {
     const RoadMeta m = S.meta[ri];
@@ -325,7 +339,7 @@ __device__ __forceinline__ void fit_group(const FArgs &a, const Stage &S, int ri
     int64_t vchi[4];
     int32_t kk[4];
     Fit f4r[4];
-    fit4<FOLD>(m, c, rel0 - rbase, S.XT, a.shift, f4r);
+    fit4<MODE>(m, c, rel0 - rbase, S.XT, a.shift, f4r);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const Fit &f = f4r[e];
@@ -362,13 +376,13 @@ __device__ __forceinline__ void fit_group(const FArgs &a, const Stage &S, int ri
 // staging order) and written on its own.  Such groups are few (at most one per road), but at
 // small roads one chunk can hold hundreds of them; one lane per combination rather than per
 // group spreads them over four times as many lanes.
-template <bool FOLD, int REC>
+template <int MODE, int REC>
 __device__ void fit_slot(const FArgs &a, const Stage &S, int r, int32_t ci, int64_t tile_start,
                          int64_t r_first) {
     const int nr = S.nr;
     while (r + 1 < nr && ci >= S.rb[r] + S.meta[r].C()) ++r;  // skips empty roads
     const int32_t k = ci - S.rb[r];
-    const Fit f = fit_combo<FOLD>(S.meta[r], S.rc[r], static_cast<uint32_t>(k), S.XT, a.shift);
+    const Fit f = fit_combo<MODE>(S.meta[r], S.rc[r], static_cast<uint32_t>(k), S.XT, a.shift);
     const bool acc = f.chi2 <= a.cut;
     const int64_t gi = tile_start + ci;
     if (REC != kRecNone) {
@@ -401,7 +415,7 @@ __device__ void fit_slot(const FArgs &a, const Stage &S, int r, int32_t ci, int6
 // lines are still in L2 (the other order leaves 16-byte holes that are filled too late and
 // reach HBM twice: 1.37x the algorithmic writes against 1.18x on a batch of 3000 events of
 // 64 roads, about 32 combinations each, when it was measured).
-template <bool FOLD, int REC>
+template <int MODE, int REC>
 __device__ void consume_listed(const FArgs &a, Stage &S) {
     const int32_t cs = S.cs, ce = S.ce, g_lo = S.g_lo, g_hi = S.g_hi;
     const int64_t tile_start = S.tile_start, r_first = S.r_first;
@@ -415,7 +429,7 @@ __device__ void consume_listed(const FArgs &a, Stage &S) {
         if (j < 4 * nx) {
             const int32_t off = S.X[j >> 2];
             const int32_t ci = ((g_lo + off) << 2) + (j & 3);
-            if (ci >= cs && ci < ce) fit_slot<FOLD, REC>(a, S, S.M[off], ci, tile_start, r_first);
+            if (ci >= cs && ci < ce) fit_slot<MODE, REC>(a, S, S.M[off], ci, tile_start, r_first);
         }
     }
     while (true) {
@@ -434,7 +448,7 @@ __device__ void consume_listed(const FArgs &a, Stage &S) {
                 in_ri |= (rel0 + e < end) ? (1u << e) : 0u;
             }
             // a group spanning a road boundary is a listed group, fitted below
-            if (!(valid & ~in_ri)) fit_group<FOLD, REC>(a, S, ri, rel0, valid, tile_start, r_first);
+            if (!(valid & ~in_ri)) fit_group<MODE, REC>(a, S, ri, rel0, valid, tile_start, r_first);
         }
     }
 }
@@ -443,7 +457,7 @@ __device__ void consume_listed(const FArgs &a, Stage &S) {
 // combinations itself, a group that spans a road boundary slot by slot.  Large roads make such
 // groups rare inside a lane's work, and keeping them in the same pass adds no extra round to
 // the chunk; small roads make them frequent, and consume_listed() is then faster.
-template <bool FOLD, int REC>
+template <int MODE, int REC>
 __device__ void consume_inline(const FArgs &a, Stage &S) {
     const int nr = S.nr;
     const int32_t cs = S.cs, ce = S.ce, g_lo = S.g_lo, g_hi = S.g_hi;
@@ -475,7 +489,7 @@ __device__ void consume_inline(const FArgs &a, Stage &S) {
             // (invalid slots compute a dummy k = 0)
             const RoadConst c = S.rc[ri];
             Fit f4r[4];
-            fit4<FOLD>(m, c, rel0 - rbase, S.XT, a.shift, f4r);
+            fit4<MODE>(m, c, rel0 - rbase, S.XT, a.shift, f4r);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const Fit &f = f4r[e];
@@ -503,7 +517,7 @@ __device__ void consume_inline(const FArgs &a, Stage &S) {
                         }
                         c = S.rc[ri];
                     }
-                    const Fit f = fit_combo<FOLD>(m, c, static_cast<uint32_t>(k), S.XT, a.shift);
+                    const Fit f = fit_combo<MODE>(m, c, static_cast<uint32_t>(k), S.XT, a.shift);
                     vp0[e] = f.v[0]; vp1[e] = f.v[1]; vp2[e] = f.v[2];
                     vc0[e] = f.v[3]; vc1[e] = f.v[4]; vc2[e] = f.v[5];
                     vchi[e] = f.chi2;
@@ -623,10 +637,17 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG == 256 ? 
         }
         set_prio((slot + iter) % 3);
         // every wave, the loader once it has staged the next chunk
-        if (listed)
-            consume_listed<FOLD, REC>(a, S[cur]);
-        else
-            consume_inline<FOLD, REC>(a, S[cur]);
+        constexpr int kWide = FOLD ? kFitFold : kFitSplit;
+        if (S[cur].narrow) {
+            if (listed)
+                consume_listed<kFitNarrow, REC>(a, S[cur]);
+            else
+                consume_inline<kFitNarrow, REC>(a, S[cur]);
+        } else if (listed) {
+            consume_listed<kWide, REC>(a, S[cur]);
+        } else {
+            consume_inline<kWide, REC>(a, S[cur]);
+        }
         __syncthreads();
         cur ^= 1;
         ++iter;
@@ -687,16 +708,20 @@ bool fused_tune_supported(const svt_tune &t) {
     const bool tile_ok = t.tile_combos >= kKeptBlock && t.tile_combos <= kMaxTile &&
                          t.tile_combos % kKeptBlock == 0;
     // the one-pass kernel's LDS holds three workgroups per CU: more would not be resident
-    const int occ_max = t.schedule == SVT_SCHEDULE_ONEPASS ? 3 : 8;
+    // (schedule 0, chosen per batch, may become the one-pass kernel)
+    const int occ_max = (t.schedule == SVT_SCHEDULE_ONEPASS || t.schedule == 0) ? 3 : 8;
     const bool occ_ok = t.wgs_per_cu >= 1 && t.wgs_per_cu <= occ_max;
-    const bool sched_ok = t.schedule == SVT_SCHEDULE_TILES || t.schedule == SVT_SCHEDULE_EVENTS ||
-                          t.schedule == SVT_SCHEDULE_ONEPASS;
+    const bool sched_ok = t.schedule == 0 || t.schedule == SVT_SCHEDULE_TILES ||
+                          t.schedule == SVT_SCHEDULE_EVENTS || t.schedule == SVT_SCHEDULE_ONEPASS;
     return wg_ok && ch_ok && tile_ok && occ_ok && sched_ok;
 }
 
 hipError_t launch_fused(const FusedLaunch &f, hipStream_t s) {
     const FArgs a = make_args(f);
-    const int grid = f.num_cus * f.tune.wgs_per_cu;
+    // persistent grid: wgs_per_cu per CU, but no more workgroups than the capacity has tiles
+    const int64_t tiles = (f.combo_cap + f.tune.tile_combos - 1) / f.tune.tile_combos;
+    const int grid = static_cast<int>(
+        std::max<int64_t>(1, std::min<int64_t>(int64_t{f.num_cus} * f.tune.wgs_per_cu, tiles)));
     if (f.tune.wg_size == 256) return launch_fused_t<256>(a, grid, s);
     if (f.tune.wg_size == 512) return launch_fused_t<512>(a, grid, s);
     return hipErrorInvalidValue;

@@ -312,21 +312,21 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
 }
 
 // Clears the error word, the work tickets (the fused kernel's tile counter is the first), the
-// kept count, the look-back status words of the blocks this pass will use and, when given,
-// zero[0 .. n_zero) (the kept list's per-block counts, which the fused kernel adds to).
+// kept count, all nb_cap look-back status words and, when given, zero[0 .. n_zero) (the kept
+// list's per-block counts, which the fused kernel adds to); copies the word count into
+// *nw_copy, where the pass's later kernels read it (the count may live in page-locked host
+// memory, and one read of it beats one per wave across the bus).
 __global__ void k_batch_reset(uint64_t *err, uint32_t *tickets, int64_t *d_n_kept,
-                              int64_t *status, int64_t nb_cap, int64_t block_words, Sizes nw,
+                              int64_t *status, int64_t nb_cap, Sizes nw, int64_t *nw_copy,
                               int64_t *zero, int64_t n_zero) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *err = SVT_NO_ERROR;
         tickets[0] = 0;
         tickets[1] = 0;
         if (d_n_kept) *d_n_kept = 0;
+        *nw_copy = nw.dev ? *nw.dev : nw.host;  // the one read of a (possibly host-side) count
     }
-    const int64_t n = load_size(nw);
-    int64_t nb = (n + block_words - 1) / block_words;
-    if (nb > nb_cap) nb = nb_cap;
-    for (int64_t i = gtid(); i < nb; i += gstride()) {
+    for (int64_t i = gtid(); i < nb_cap; i += gstride()) {
         status[i] = 0;
         status[nb_cap + i] = 0;
     }
@@ -365,14 +365,14 @@ hipError_t launch_prepass(const PrepassLaunch &p, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch_reset(const PrepassLaunch &p, int64_t block_words, int64_t *d_n_kept,
+hipError_t launch_batch_reset(const PrepassLaunch &p, int64_t *nw_copy, int64_t *d_n_kept,
                               int64_t *zero, int64_t n_zero, hipStream_t s) {
     const int64_t items = zero && n_zero > p.nb_cap ? n_zero : p.nb_cap;
     int64_t blocks = (items + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(k_batch_reset, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
-                       p.err, p.tickets, d_n_kept, p.status, p.nb_cap, block_words, p.nw, zero,
+                       p.err, p.tickets, d_n_kept, p.status, p.nb_cap, p.nw, nw_copy, zero,
                        zero ? n_zero : 0);
     return hipGetLastError();
 }

@@ -697,7 +697,9 @@ __global__ __launch_bounds__(kSegThreads) void k_kept_refit(
 
 // The header and the first n_roads per-road results of a batch, back to back in one buffer
 // (layout in svt_gather_results).  When the buffer is host memory every store crosses the bus
-// once; the closing system-scope fence makes them visible to the host with the kernel's end.
+// once; a closing system-scope fence in every thread that stored makes them visible to the
+// host with the kernel's end (the grid is sized for the capacity, and the threads past the
+// batch's roads store nothing and skip the costly fence).
 __global__ void k_gather(svt_roads roads, svt_best best, int64_t road_cap, const int64_t *n_words,
                          const int64_t *n_roads, const int64_t *n_combos, const int64_t *n_kept,
                          const uint64_t *err, int64_t *out, int64_t out_roads) {
@@ -721,7 +723,7 @@ __global__ void k_gather(svt_roads roads, svt_best best, int64_t road_cap, const
             for (int a = 0; a < 7; ++a) col[a * nr + i] = src[a][i];
         }
     }
-    __threadfence_system();
+    if (gtid() == 0 || gtid() < nr) __threadfence_system();
 }
 
 inline int64_t clamp_grid(int64_t blocks, int64_t maxb) {

@@ -229,13 +229,23 @@ class BatchRunner:
             if nbytes < 0:
                 raise ValueError("unsupported tune / capacities")
             self.work = _ws(nbytes, d)
-        d_n_words = self.d_n[0:1] if n_words_ptr is None else n_words_ptr
-        self._call = L.PreparedBatch(self.bank, self.cfg, self.tune, d_n_words, self.word_cap,
-                                     self.roads, self.road_cap, self.rec, self.accept,
-                                     self.combo_cap, self.best, self.kept, self.kept_cap,
-                                     self.d_n[1:2], self.d_n[2:3],
-                                     self.d_n[3:4] if self.kept_cap > 0 else None, self.d_err,
-                                     self.work)
+        self._d_n_words = self.d_n[0:1] if n_words_ptr is None else n_words_ptr
+        self._calls = {}
+        self._call = self._prepared(self.word_cap)
+
+    def _prepared(self, word_cap: int):
+        """The prepared argument list for a word capacity up to the runner's own (a smaller one
+        sizes the launch grids and look-back state to batches that fit it)."""
+        call = self._calls.get(word_cap)
+        if call is None:
+            call = L.PreparedBatch(self.bank, self.cfg, self.tune, self._d_n_words, word_cap,
+                                   self.roads, self.road_cap, self.rec, self.accept,
+                                   self.combo_cap, self.best, self.kept, self.kept_cap,
+                                   self.d_n[1:2], self.d_n[2:3],
+                                   self.d_n[3:4] if self.kept_cap > 0 else None, self.d_err,
+                                   self.work)
+            self._calls[word_cap] = call
+        return call
 
     def load(self, words: torch.Tensor, n_words: Optional[int] = None):
         """Copy a batch of words into the resident buffer and set the device word count."""
@@ -257,14 +267,22 @@ class BatchRunner:
         self.n_words = n
         return self
 
-    def run(self, stream=None, words=None):
+    def run(self, stream=None, words=None, word_cap: Optional[int] = None):
         """One pass over the batch.  ``words``: another word buffer the kernels can read
         (a device tensor, or the device address of mapped host memory), default the
-        resident one."""
+        resident one.  ``word_cap``: the capacity the pass is launched for (at least the
+        batch's word count, at most the runner's; default the runner's): with graphs, each
+        distinct value is one cached graph."""
         s = stream if stream is not None else self.stream
         src = self.words if words is None else words
-        st = self._call(src, (L.SVT_BATCH_GRAPH if self.graph else 0) |
-                        (L.SVT_BATCH_KEPT_ONLY if self.kept_only else 0), s)
+        if word_cap is None or word_cap == self.word_cap:
+            call = self._call
+        elif 0 <= word_cap <= self.word_cap:
+            call = self._prepared(int(word_cap))
+        else:
+            raise ValueError(f"word_cap {word_cap} outside 0..{self.word_cap}")
+        st = call(src, (L.SVT_BATCH_GRAPH if self.graph else 0) |
+                  (L.SVT_BATCH_KEPT_ONLY if self.kept_only else 0), s)
         L.check(st, "svt_process_batch" if self.work is not None else "svt_process_batch_static")
         return self
 

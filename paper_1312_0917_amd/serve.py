@@ -53,9 +53,32 @@ class ServeStats:
     max_loop_gap_s: float = 0.0   # longest time between two passes of the host loop
     max_service_s: float = 0.0    # longest launch-to-done time of one batch
     max_service_batch: int = 0    # events in that batch
+    # per event, from its batch: seconds waiting in the FIFO (arrival to the launch call), in
+    # the host's launch call, on the device (first to last operation of the batch on its
+    # stream, transfers included; NaN when the slot does not time it) and from the end of the
+    # launch call to the host seeing the results, less the device time (launch latency plus
+    # how long the finished batch waited for the loop to poll it)
+    queue_s: Optional[np.ndarray] = None
+    enqueue_s: Optional[np.ndarray] = None
+    device_s: Optional[np.ndarray] = None
+    visible_s: Optional[np.ndarray] = None
 
     def percentile_us(self, q) -> float:
         return float(np.percentile(self.latency_s, q) * 1e6)
+
+    def breakdown(self, warmup_events: int = 0) -> Optional[dict]:
+        """p50 / p99 / mean in microseconds of each latency component (see the fields)."""
+        if self.queue_s is None:
+            return None
+        out = {}
+        for name in ("queue", "enqueue", "device", "visible"):
+            v = getattr(self, name + "_s")[warmup_events:]
+            v = v[np.isfinite(v)]
+            if v.size:
+                out[name] = dict(p50_us=round(float(np.percentile(v, 50)) * 1e6, 2),
+                                 p99_us=round(float(np.percentile(v, 99)) * 1e6, 2),
+                                 mean_us=round(float(v.mean()) * 1e6, 2))
+        return out
 
     def summary(self, warmup_events: int = 0) -> dict:
         lat = self.latency_s[warmup_events:]
@@ -69,7 +92,8 @@ class ServeStats:
                     retries=self.retries,
                     max_loop_gap_us=round(self.max_loop_gap_s * 1e6, 2),
                     max_service_us=round(self.max_service_s * 1e6, 2),
-                    max_service_batch=self.max_service_batch)
+                    max_service_batch=self.max_service_batch,
+                    breakdown=self.breakdown(warmup_events))
 
 
 def serve(stream: EventStream, slots: Sequence, max_events: int = 256,
@@ -96,10 +120,11 @@ def serve(stream: EventStream, slots: Sequence, max_events: int = 256,
 def _serve(stream, slots, max_events, clock, keep_results, idle_sleep_s):
     n = stream.n_events
     lat = np.full(n, np.nan)
+    q_s, enq_s, dev_s, vis_s = (np.full(n, np.nan) for _ in range(4))
     results = [None] * n if keep_results else None
     fifo = deque()
     nxt = 0
-    busy = {}  # slot index -> (e0, e1, launch time)
+    busy = {}  # slot index -> (e0, e1, launch-call start, launch-call end)
     batch_sizes = []
     total_combos = 0
     done = 0
@@ -117,13 +142,18 @@ def _serve(stream, slots, max_events, clock, keep_results, idle_sleep_s):
         progressed = False
         for si in list(busy):
             if slots[si].poll():
-                e0, e1, t_launch = busy.pop(si)
+                e0, e1, t_launch, t_enq = busy.pop(si)
                 t_done = clock() - t0
                 if t_done - t_launch > max_service:
                     max_service, max_service_batch = t_done - t_launch, e1 - e0
                 nc, per_event = slots[si].collect()
                 total_combos += nc
                 lat[e0:e1] = t_done - stream.arrival_s[e0:e1]
+                q_s[e0:e1] = t_launch - stream.arrival_s[e0:e1]
+                enq_s[e0:e1] = t_enq - t_launch
+                dev = getattr(slots[si], "last_device_s", float("nan"))
+                dev_s[e0:e1] = dev
+                vis_s[e0:e1] = t_done - t_enq - (dev if np.isfinite(dev) else 0.0)
                 if keep_results:
                     for i, r in enumerate(per_event):
                         results[e0 + i] = r
@@ -142,8 +172,9 @@ def _serve(stream, slots, max_events, clock, keep_results, idle_sleep_s):
                 raise RuntimeError(f"event {e0} does not fit an empty slot")
             for _ in range(e1 - e0):
                 fifo.popleft()
+            t_launch = clock() - t0
             slot.launch(stream.slice(e0, e1), e0, e1)
-            busy[si] = (e0, e1, clock() - t0)
+            busy[si] = (e0, e1, t_launch, clock() - t0)
             batch_sizes.append(e1 - e0)
             progressed = True
         if not progressed:
@@ -158,7 +189,8 @@ def _serve(stream, slots, max_events, clock, keep_results, idle_sleep_s):
     stats = ServeStats(latency_s=lat, batch_sizes=batch_sizes, n_combos=total_combos, wall_s=wall,
                        retries=sum(getattr(s, "retries", 0) for s in slots),
                        max_loop_gap_s=max_gap, max_service_s=max_service,
-                       max_service_batch=max_service_batch)
+                       max_service_batch=max_service_batch, queue_s=q_s, enqueue_s=enq_s,
+                       device_s=dev_s, visible_s=vis_s)
     return stats, results
 
 
@@ -180,13 +212,22 @@ class GpuSlot:
 
     ``io="copy"``: pinned words -> H2D -> graph replay -> D2H in two steps (the sizes and error
     word first, then exactly n_roads entries of each per-road array), kept for comparison.
+
+    ``size_to_batch`` (default): each batch is launched for the smallest power-of-two word
+    capacity (at least ``MIN_LAUNCH_WORDS``) that holds it, not for the slot's whole capacity,
+    so the persistent grids and look-back state match the batch; with graphs that is one
+    cached graph per capacity (``warm`` captures them all).  A zero schedule in ``tune`` is
+    then chosen per launch capacity, which puts small batches on the one-pass kernel.
     """
+
+    MIN_LAUNCH_WORDS = 4096
 
     BEST_KEYS = ("n_accept", "k", "p0", "p1", "p2", "chi2")
     IN_HEADER = 256  # bytes before the words in the mapped input buffer (word count first)
 
     def __init__(self, cfg, bank, word_cap: int, road_cap: int, combo_cap: int, tune=None,
-                 graph: bool = True, keep_results: bool = False, io: str = "mapped"):
+                 graph: bool = True, keep_results: bool = False, io: str = "mapped",
+                 timing: bool = False, size_to_batch: bool = True):
         import torch
 
         from . import _lib as L
@@ -197,6 +238,7 @@ class GpuSlot:
         self.torch, self.L, self.io = torch, L, io
         self.word_cap, self.road_cap, self.combo_cap = word_cap, road_cap, combo_cap
         self.keep = keep_results
+        self.size_to_batch = size_to_batch
         if io == "mapped":
             self.h_in = torch.empty(self.IN_HEADER + 4 * word_cap, dtype=torch.uint8,
                                     pin_memory=True)
@@ -233,9 +275,14 @@ class GpuSlot:
             self._fetch += [(self.runner.roads["event"], self.h_event, 4),
                             (self.runner.roads["set"], self.h_set, 4)]
         self.stream = self.runner.stream
+        # timing: one more event before the batch's first operation, and a timed done event;
+        # last_device_s = the batch's time on the device (NaN without timing)
+        self.timing = timing
+        self.last_device_s = float("nan")
         self.sizes_ev = torch.cuda.Event()
-        self.done_ev = torch.cuda.Event()
-        for ev in (self.sizes_ev, self.done_ev):  # create the events
+        self.done_ev = torch.cuda.Event(enable_timing=timing)
+        self.start_ev = torch.cuda.Event(enable_timing=True) if timing else None
+        for ev in (self.sizes_ev, self.done_ev) + ((self.start_ev,) if timing else ()):
             ev.record(self.stream)
         torch.cuda.synchronize()
         self.retries = 0
@@ -249,20 +296,49 @@ class GpuSlot:
         # batch that overflows is split and run again
         return n_words <= self.word_cap
 
-    def _enqueue(self, words: np.ndarray):
+    def launch_cap(self, n_words: int) -> int:
+        """Word capacity a batch of n_words is launched for."""
+        if not self.size_to_batch:
+            return self.word_cap
+        c = self.MIN_LAUNCH_WORDS
+        while c < n_words:
+            c *= 2
+        return min(c, self.word_cap)
+
+    def launch_caps(self):
+        """Every capacity launch_cap can return."""
+        caps = {self.word_cap}
+        c = self.MIN_LAUNCH_WORDS
+        while self.size_to_batch and c < self.word_cap:
+            caps.add(c)
+            c *= 2
+        return sorted(caps)
+
+    def warm(self, words: np.ndarray):
+        """Run a small batch once per launch capacity (captures every graph before timing)."""
+        for cap in self.launch_caps():
+            self.batch = (words, 0, 1)
+            self._enqueue(words, cap)
+            self._wait()
+            self.collect()
+
+    def _enqueue(self, words: np.ndarray, cap: Optional[int] = None):
         L, r, s = self.L, self.runner, self.stream
         n = len(words)
+        cap = self.launch_cap(n) if cap is None else cap
         self.h_words_np[:n] = words
         self.h_n_np[0] = n
+        if self.timing:
+            L.svt_event_record(self.start_ev, s)
         if self.io == "mapped":
-            r.run(words=self.d_words)
+            r.run(words=self.d_words, word_cap=cap)
             self._gather(s)
             L.svt_event_record(self.done_ev, s)
             self.stage = 2
             return
         L.svt_copy_async(r.d_n, self.h_n, 8, L.SVT_COPY_H2D, s)
         L.svt_copy_async(r.words, self.h_words, 4 * n, L.SVT_COPY_H2D, s)
-        r.run()
+        r.run(word_cap=cap)
         L.svt_copy_async(self.h_state, r.d_state, 40, L.SVT_COPY_D2H, s)
         L.svt_event_record(self.sizes_ev, s)
         self.stage = 1
@@ -323,6 +399,8 @@ class GpuSlot:
     def collect(self):
         L = self.L
         words, e0, e1 = self.batch
+        if self.timing:
+            self.last_device_s = self.start_ev.elapsed_time(self.done_ev) * 1e-3
         st, idx = self._error()
         sizes, _ = self._sizes_err()
         if st == L.SVT_ERR_CAPACITY and e1 - e0 > 1:

@@ -146,9 +146,9 @@ def test_product_path_does_not_import_the_oracle():
 
 
 def test_tune_resolution_fills_defaults_and_rejects_unbuilt_shapes():
-    t = L.svt_tune_resolve()  # the built-in schedule is the one-pass kernel
+    t = L.svt_tune_resolve()  # schedule 0: chosen per call from the word capacity
     assert (t.tile_combos, t.chunk_roads, t.wg_size, t.wgs_per_cu, t.schedule) == \
-        (4096, 64, 256, 3, L.SVT_SCHEDULE_ONEPASS)
+        (4096, 64, 256, 3, 0)
     t = L.svt_tune_resolve(L.make_tune(8192, 0, 512, 0, 1))
     assert (t.tile_combos, t.chunk_roads, t.wg_size, t.wgs_per_cu, t.schedule) == (8192, 64, 512, 3, 1)
     t = L.svt_tune_resolve(L.make_tune(8192, 0, 0, 4, L.SVT_SCHEDULE_TILES))
@@ -156,7 +156,8 @@ def test_tune_resolution_fills_defaults_and_rejects_unbuilt_shapes():
     for bad in [L.make_tune(wg_size=128), L.make_tune(tile_combos=6000),
                 L.make_tune(chunk_roads=32), L.make_tune(wgs_per_cu=9), L.make_tune(schedule=4),
                 # the one-pass kernel's LDS holds three workgroups per CU
-                L.make_tune(wgs_per_cu=4, schedule=L.SVT_SCHEDULE_ONEPASS)]:
+                L.make_tune(wgs_per_cu=4, schedule=L.SVT_SCHEDULE_ONEPASS),
+                L.make_tune(wgs_per_cu=4)]:  # schedule 0 may become the one-pass kernel
         with pytest.raises(L.SvtError):
             L.svt_tune_resolve(bad)
 
