@@ -128,7 +128,8 @@ typedef struct svt_best {
 /* Launch parameters of the batched pass; zeros pick the built-in defaults. */
 typedef struct svt_tune {
     int32_t tile_combos;  /* two-kernel schedule: combinations per work tile, 4096 or 8192 */
-    int32_t chunk_roads;  /* two-kernel schedule: roads staged in LDS at once, 64 */
+    int32_t chunk_roads;  /* two-kernel schedule: roads staged in LDS at once at most: 16, 32
+                             or 64 (fewer when their hits or pair tables fill the stage) */
     int32_t wg_size;      /* two-kernel schedule: 256 or 512 (one loader wave, the rest fit) */
     int32_t wgs_per_cu;   /* persistent workgroups per compute unit, 1..8 (one pass: 1..3);
                              the two-kernel schedule launches no more workgroups than

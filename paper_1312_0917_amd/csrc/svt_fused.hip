@@ -27,7 +27,7 @@
 namespace svt {
 namespace {
 
-constexpr int kChunk = 64;             // roads staged per chunk: one loader lane each
+constexpr int kChunk = 64;             // roads staged per chunk at most: one loader lane each
 constexpr int kWordCap = 2048;         // coordinates staged per chunk (a road has at most 40)
 constexpr int kTabCap = 2048;          // coordinate-pair table entries per chunk (<= 136/road)
 constexpr int kMapCap = kMaxTile / 4;  // groups of 4 combinations in a tile
@@ -57,6 +57,7 @@ struct FArgs {
     int64_t combo_cap;
     int32_t records;        // 0: kept-only mode, no per-combination records
     int32_t fold;           // shift <= 15: ql packed with f_j4 (see fit_xyz)
+    int32_t chunk_roads;    // roads staged per chunk (16, 32 or kChunk)
     int32_t num_cus;        // CUs of the device (the grid holds wgs_per_cu workgroups per CU)
 };
 
@@ -145,7 +146,8 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
         const int32_t ntab = (valid && C > 0) ? n0 * n1 + n2 * n3 + n4 : 0;
         const int32_t wend = wave_incl_scan(nwords), tend = wave_incl_scan(ntab);
         const int32_t wo = wend - nwords, to = tend - ntab;
-        const bool fits = valid && wend <= kWordCap && tend <= kTabCap;  // a prefix of lanes
+        const bool fits = valid && lane < a.chunk_roads && wend <= kWordCap &&
+                          tend <= kTabCap;  // a prefix of lanes
         const int nr = __popcll(__ballot(fits));
         if (nr == 0) {  // tile finished: continue with the ticket fetched during it
             if (L.need_ticket) {  // (never set when no tile lies past the grid: the ticket then
@@ -677,6 +679,7 @@ FArgs make_args(const FusedLaunch &f) {
     a.combo_cap = f.combo_cap;
     a.records = f.kept_only ? 0 : 1;
     a.fold = f.cfg.shift <= 15 ? 1 : 0;
+    a.chunk_roads = f.tune.chunk_roads;
     a.num_cus = f.num_cus;
     return a;
 }
@@ -704,7 +707,7 @@ hipError_t launch_fused_t(const FArgs &a, int grid, hipStream_t s) {
 
 bool fused_tune_supported(const svt_tune &t) {
     const bool wg_ok = t.wg_size == 256 || t.wg_size == 512;
-    const bool ch_ok = t.chunk_roads == kChunk;
+    const bool ch_ok = t.chunk_roads == 16 || t.chunk_roads == 32 || t.chunk_roads == kChunk;
     const bool tile_ok = t.tile_combos >= kKeptBlock && t.tile_combos <= kMaxTile &&
                          t.tile_combos % kKeptBlock == 0;
     // the one-pass kernel's LDS holds three workgroups per CU: more would not be resident

@@ -67,7 +67,7 @@ def test_workspace_sizes_are_aligned_and_monotone():
     assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, t) > 0
     assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, L.make_tune(1000, 64, 256, 4)) == -1
     assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, L.make_tune(16384, 64, 256, 4)) == -1
-    assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, L.make_tune(8192, 32, 256, 4)) == -1
+    assert L.svt_batch_workspace(1 << 20, 1 << 16, 1 << 22, L.make_tune(8192, 48, 256, 4)) == -1
     # the batched path holds at most 2^31 - 1 words per batch
     assert L.svt_batch_workspace((1 << 31) - 1, 1 << 16, 1 << 22, t) > 0
     assert L.svt_batch_workspace(1 << 31, 1 << 16, 1 << 22, t) == -1
@@ -154,7 +154,7 @@ def test_tune_resolution_fills_defaults_and_rejects_unbuilt_shapes():
     t = L.svt_tune_resolve(L.make_tune(8192, 0, 0, 4, L.SVT_SCHEDULE_TILES))
     assert (t.tile_combos, t.wgs_per_cu, t.schedule) == (8192, 4, L.SVT_SCHEDULE_TILES)
     for bad in [L.make_tune(wg_size=128), L.make_tune(tile_combos=6000),
-                L.make_tune(chunk_roads=32), L.make_tune(wgs_per_cu=9), L.make_tune(schedule=4),
+                L.make_tune(chunk_roads=48), L.make_tune(wgs_per_cu=9), L.make_tune(schedule=4),
                 # the one-pass kernel's LDS holds three workgroups per CU
                 L.make_tune(wgs_per_cu=4, schedule=L.SVT_SCHEDULE_ONEPASS),
                 L.make_tune(wgs_per_cu=4)]:  # schedule 0 may become the one-pass kernel

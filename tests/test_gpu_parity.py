@@ -23,6 +23,7 @@ TUNES = [L.make_tune(wgs_per_cu=1, schedule=ONEPASS), L.make_tune(wgs_per_cu=2, 
          L.make_tune(4096, 64, 256, 2, TILES), L.make_tune(8192, 64, 256, 3, TILES),
          L.make_tune(4096, 64, 256, 4, TILES),  # a fourth workgroup per CU: a fourth priority slot
          L.make_tune(4096, 64, 512, 1, TILES), L.make_tune(8192, 64, 512, 2, TILES),
+         L.make_tune(4096, 32, 256, 3, TILES), L.make_tune(8192, 16, 512, 2, TILES),
          L.make_tune(4096, 64, 256, 4, EVENTS)]  # the last: one event per workgroup
 
 
@@ -118,6 +119,54 @@ def test_tiny_random_streams(bank, seed):
     compare(ref, run_plain(words, f, q, cfg), PLAIN_KEYS, f"plain tiny {seed}")
     got, _ = run_batch(words, f, q, cfg, ref=ref, tune=TUNES[seed % len(TUNES)], graph=False)
     compare(ref, got, BATCH_KEYS, f"batch tiny {seed}")
+
+
+def test_narrow_fit_form_at_its_bounds(bank):
+    """The fused kernel's narrow form (whole offset in the int32 accumulator, chi-square summed
+    in 32 bits) on constant sets exactly at its bounds, and one step past them (wide form).
+
+    Set 0: rows 0-2 have 4096 * sum|f| + |q| = 2^31 - 1, and coordinates of -4096 against
+    f = -32767 drive the row sum to exactly INT32_MAX; rows 3-5 have chi-square components up
+    to 32766 in magnitude, so the sum of their squares passes 2^31 (the unsigned 32-bit sum).
+    Sets 1 and 2 exceed the chi-square bound and the int32 bound by one and take the wide
+    form.  A chunk holding any of them is fitted wide: the first four events (16 roads) use
+    only sets 0 and 3, so with 16 roads per chunk their chunk is narrow, and with 64 roads per
+    chunk everything is fitted wide."""
+    f = np.zeros((256, 6, 5), np.int64)
+    q = np.zeros((256, 6), np.int64)
+    f[:, :, :] = np.random.default_rng(5).integers(-50, 51, size=(256, 6, 5))
+    for s_ in range(3):
+        f[s_, 0:3, :] = -32767
+        q[s_, 0:3] = 2**31 - 1 - 4096 * 5 * 32767
+        f[s_, 3:6, :] = 0
+        f[s_, 3:6, 0] = [8191, -8191, 8191]
+        q[s_, 3:6] = 33553407 - 4096 * 8191  # (B >> 10) + 1 = 32767
+    q[1, 4] += 1024        # chi-square bound passed by one step of the shift
+    q[2, 1] += 1           # int32 bound passed by one
+    assert np.all(np.abs(f) <= 32767) and np.all(np.abs(q) < 2**31)
+    f, q = f.astype(np.int16), q.astype(np.int32)
+    rng = np.random.default_rng(6)
+    events = []
+    for e in range(6):
+        roads = []
+        for r, st in enumerate([0, 3, 0, 3] if e < 4 else [1, 2, 0, 3]):
+            coords = [-4096] * 5 if (e + r) % 2 == 0 else [4095] * 5
+            hits = [(l, coords[l]) for l in range(5)]
+            hits += [(l, int(rng.integers(-4096, 4096))) for l in range(5)
+                     for _ in range(int(rng.integers(0, 3)))]
+            roads.append((st, [hits[i] for i in rng.permutation(len(hits))]))
+        events.append(roads)
+    words = stream(events)
+    cfg = oracle.make_config(chi2_cut=2**62, shift=10)
+    ref = oracle.run(words, f, q, cfg)
+    p0 = np.asarray(ref["p0"]).astype(np.int64)
+    chi2 = np.asarray(ref["chi2"]).astype(np.int64)
+    first = int(np.asarray(ref["road_combo_begin"])[16])  # combinations of the first 16 roads
+    assert p0[:first].max() == (2**31 - 1) >> 10  # a row sum reached INT32_MAX
+    assert chi2[:first].max() > 2**31             # the 32-bit chi-square sum passed 2^31
+    for t in (L.make_tune(4096, 16, 256, 3, TILES), L.make_tune(8192, 64, 256, 2, TILES)):
+        got, _ = run_batch(words, f, q, cfg, ref=ref, tune=t, graph=False)
+        compare(ref, got, BATCH_KEYS, f"narrow bounds chunk {t.chunk_roads}")
 
 
 @pytest.mark.parametrize("extreme", [False, True])
