@@ -21,7 +21,8 @@
 // to HBM to be read again; the only other launch of a pass is the reset of the look-back state.
 //
 // Units: workgroup w takes unit w first, then units gridDim.x + t from a ticket counter,
-// fetched while it finishes the previous unit.  Units taken from tickets run in ticket order,
+// fetched while it finishes the previous unit (a ticket taken earlier reserves a unit that later
+// units' look-backs then wait on until it starts).  Units taken from tickets run in ticket order,
 // so a unit only waits on units already taken; the first units are numbered by the grid, and a
 // look-back that has waited too long on one of them computes that unit's counts itself.
 //
@@ -140,10 +141,11 @@ __device__ __forceinline__ void pack_set(const svt_fconst &F, BankT<FOLD> &B, in
     }
 }
 
-// Parameters of combination k of a road, fitted from the grouped coordinates in LDS with the
-// plain int64 arithmetic of the definition (the same values as the records).
-__device__ inline int64_t refit_lds(const svt_fconst &F, const int16_t *sc, int32_t shift,
-                                    uint32_t nh, int32_t hb, uint32_t k, int32_t *v) {
+// Fit combination k of a road from the grouped coordinates and the road's packed constant set in
+// LDS, with the records' own arithmetic (so the values equal the records bit for bit).
+template <bool FOLD>
+__device__ __forceinline__ Fit refit_packed(const BankT<FOLD> &c, const int16_t *sc, uint32_t nh,
+                                            int32_t hb, uint32_t k, int32_t shift) {
     uint32_t h[SVT_N_LAYERS];
 #pragma unroll
     for (int l = SVT_N_LAYERS - 1; l >= 0; --l) {  // layer 0 most significant
@@ -158,16 +160,7 @@ __device__ inline int64_t refit_lds(const svt_fconst &F, const int16_t *sc, int3
         x[l] = sc[off + static_cast<int32_t>(h[l])];
         off += static_cast<int32_t>(nh_of(nh, l));
     }
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        int64_t acc = F.q[j];
-#pragma unroll
-        for (int l = 0; l < SVT_N_LAYERS; ++l)
-            acc += static_cast<int64_t>(F.f[j][l]) * static_cast<int64_t>(x[l]);
-        v[j] = static_cast<int32_t>(acc >> shift);
-    }
-    return static_cast<int64_t>(v[3]) * v[3] + static_cast<int64_t>(v[4]) * v[4] +
-           static_cast<int64_t>(v[5]) * v[5];
+    return fit_xyz<FOLD>(c, pack16(x[0], x[1]), pack16(x[2], x[3]), pack16(x[4], 1), shift);
 }
 
 // ---- one chunk of the unit's combinations ---------------------------------------------------
@@ -817,7 +810,7 @@ __global__ __launch_bounds__(kOT) __attribute__((amdgpu_waves_per_eu(FOLD ? 3 : 
             if (r >= a.road_cap) continue;
             const uint32_t info = S.fr_info[fi];
             const uint32_t nh = info & 0xFFFFFu;
-            const svt_fconst &F = a.bank[info >> 20];
+            const BankT<FOLD> &F = S.bank[info >> 20];
             const int32_t hb = S.fr_hb[fi];
             unsigned long long key = can_fit ? S.fr_key[fi] : ~0ull;
             int32_t bk = -1;
@@ -826,9 +819,8 @@ __global__ __launch_bounds__(kOT) __attribute__((amdgpu_waves_per_eu(FOLD ? 3 : 
                 // saturated key (chi2 >= 2^49 - 1, extreme constants only): exact rescan
                 const int64_t C = combos_of(nh);
                 for (int64_t k = 0; k < C; ++k) {
-                    int32_t vv[6];
-                    const int64_t c2 = refit_lds(F, S.sc, shift, nh, hb,
-                                                 static_cast<uint32_t>(k), vv);
+                    const int64_t c2 =
+                        refit_packed<FOLD>(F, S.sc, nh, hb, static_cast<uint32_t>(k), shift).chi2;
                     if (c2 <= a.cfg.chi2_cut && c2 < bchi) {
                         bchi = c2;
                         bk = static_cast<int32_t>(k);
@@ -842,11 +834,10 @@ __global__ __launch_bounds__(kOT) __attribute__((amdgpu_waves_per_eu(FOLD ? 3 : 
             a.best.k[r] = bk;
             a.best.chi2[r] = bchi;
             if (bk >= 0) {
-                int32_t vv[6];
-                refit_lds(F, S.sc, shift, nh, hb, static_cast<uint32_t>(bk), vv);
-                a.best.p0[r] = vv[0];
-                a.best.p1[r] = vv[1];
-                a.best.p2[r] = vv[2];
+                const Fit f = refit_packed<FOLD>(F, S.sc, nh, hb, static_cast<uint32_t>(bk), shift);
+                a.best.p0[r] = f.v[0];
+                a.best.p1[r] = f.v[1];
+                a.best.p2[r] = f.v[2];
             } else {
                 a.best.p0[r] = INT32_MIN;
                 a.best.p1[r] = INT32_MIN;
