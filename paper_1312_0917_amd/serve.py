@@ -194,6 +194,25 @@ def _serve(stream, slots, max_events, clock, keep_results, idle_sleep_s):
     return stats, results
 
 
+def launch_capacity(n_words: int, word_cap: int, min_words: int) -> int:
+    """The smallest power-of-two word capacity, at least min_words, that holds n_words, capped at
+    word_cap: the capacity a batch is launched for when launches are sized to the batch."""
+    c = min_words
+    while c < n_words:
+        c *= 2
+    return min(c, word_cap)
+
+
+def launch_capacities(word_cap: int, min_words: int) -> list:
+    """Every value launch_capacity can return for batches up to word_cap words."""
+    caps = {word_cap}
+    c = min_words
+    while c < word_cap:
+        caps.add(c)
+        c *= 2
+    return sorted(caps)
+
+
 def split_by_event(road_event: np.ndarray, arrays: dict, n_events: int) -> list:
     """Per-road result arrays of one batch -> list of per-event dicts (event ordinal in batch)."""
     bounds = np.searchsorted(road_event, np.arange(n_events + 1))
@@ -300,19 +319,13 @@ class GpuSlot:
         """Word capacity a batch of n_words is launched for."""
         if not self.size_to_batch:
             return self.word_cap
-        c = self.MIN_LAUNCH_WORDS
-        while c < n_words:
-            c *= 2
-        return min(c, self.word_cap)
+        return launch_capacity(n_words, self.word_cap, self.MIN_LAUNCH_WORDS)
 
     def launch_caps(self):
         """Every capacity launch_cap can return."""
-        caps = {self.word_cap}
-        c = self.MIN_LAUNCH_WORDS
-        while self.size_to_batch and c < self.word_cap:
-            caps.add(c)
-            c *= 2
-        return sorted(caps)
+        if not self.size_to_batch:
+            return [self.word_cap]
+        return launch_capacities(self.word_cap, self.MIN_LAUNCH_WORDS)
 
     def warm(self, words: np.ndarray):
         """Run a small batch once per launch capacity (captures every graph before timing)."""

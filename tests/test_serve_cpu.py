@@ -103,3 +103,39 @@ def test_packet_sizes_pick_leading_events():
     assert transfer.packet_events(ewb, 404) == 2
     assert transfer.packet_events(ewb, 1600) == 3
     assert transfer.packet_events(ewb, 10**9) == 4      # everything
+
+
+class TimedFakeSlot(FakeSlot):
+    """A fake slot that reports a device time for each batch, as a timing GPU slot does."""
+
+    def collect(self):
+        self.last_device_s = self.delay / 2
+        return super().collect()
+
+
+def test_latency_breakdown_adds_up(stream_and_bank):
+    """queue + enqueue + device + visible is each event's latency, every part from its batch."""
+    st, s, bank = stream_and_bank
+    slots = [TimedFakeSlot(bank, 40000, 1e-3, time.perf_counter) for _ in range(2)]
+    stats, _ = serve.serve(st, slots, max_events=16)
+    total = stats.queue_s + stats.enqueue_s + stats.device_s + stats.visible_s
+    assert np.allclose(total, stats.latency_s, rtol=0, atol=1e-9)
+    assert np.all(stats.queue_s >= 0) and np.all(stats.enqueue_s >= 0)
+    assert np.allclose(stats.device_s, 0.5e-3)
+    b = stats.summary()["breakdown"]
+    assert set(b) == {"queue", "enqueue", "device", "visible"}
+    # slots that time nothing leave the device part out of the breakdown
+    plain = serve.serve(st, [FakeSlot(bank, 40000, 1e-3, time.perf_counter)], max_events=16)[0]
+    assert np.isnan(plain.device_s).all() and "device" not in plain.summary()["breakdown"]
+
+
+def test_launch_capacity_is_the_smallest_power_of_two_that_holds_the_batch():
+    assert serve.launch_capacity(1, 700000, 4096) == 4096
+    assert serve.launch_capacity(4096, 700000, 4096) == 4096
+    assert serve.launch_capacity(4097, 700000, 4096) == 8192
+    assert serve.launch_capacity(600000, 700000, 4096) == 700000  # capped at the slot
+    caps = serve.launch_capacities(700000, 4096)
+    assert caps == [4096 << i for i in range(8)] + [700000]
+    for n in (1, 5000, 70000, 524288, 524289, 700000):
+        assert serve.launch_capacity(n, 700000, 4096) in caps
+        assert serve.launch_capacity(n, 700000, 4096) >= n
