@@ -115,6 +115,13 @@ svt_tune resolve_tune(const svt_tune *t, int64_t word_cap = -1) {
     return r;
 }
 
+// A tune is valid when its fields are, before the capacity picks a zero schedule (which must
+// then suit both schedules), and after.
+bool tune_ok(const svt_tune *t, int64_t word_cap) {
+    return fused_tune_supported(resolve_tune(t)) &&
+           fused_tune_supported(resolve_tune(t, word_cap));
+}
+
 int num_cus() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -210,7 +217,7 @@ svt_status svt_tune_resolve(const svt_tune *tune, svt_tune *out) {
 svt_status svt_tune_for_batch(const svt_tune *tune, int64_t word_cap, svt_tune *out) {
     if (!out || word_cap < 0) return SVT_ERR_ARG;
     *out = resolve_tune(tune, word_cap);
-    return fused_tune_supported(*out) ? SVT_OK : SVT_ERR_ARG;
+    return tune_ok(tune, word_cap) ? SVT_OK : SVT_ERR_ARG;
 }
 
 const char *svt_status_name(svt_status s) {
@@ -263,7 +270,7 @@ int64_t svt_batch_workspace(int64_t word_cap, int64_t road_cap, int64_t combo_ca
                             const svt_tune *tune) {
     if (word_cap < 0 || word_cap > kMaxBatchWords || road_cap < 0 || combo_cap < 0) return -1;
     const svt_tune t = resolve_tune(tune, word_cap);
-    if (!fused_tune_supported(t)) return -1;
+    if (!tune_ok(tune, word_cap)) return -1;
     Carver c{nullptr};
     carve_batch(c, word_cap, road_cap, combo_cap, t.tile_combos);
     return c.used;
@@ -536,7 +543,7 @@ svt_status process_batch(const svt_fconst *bank, const svt_config *cfg, const sv
         if (p && !aligned(p, 16)) return SVT_ERR_ARG;
     if (!aligned(accept, 4)) return SVT_ERR_ARG;
     const svt_tune t = resolve_tune(tune, word_cap);
-    if (!fused_tune_supported(t)) return SVT_ERR_ARG;
+    if (!tune_ok(tune, word_cap)) return SVT_ERR_ARG;
     if (work_bytes == kStaticWork) {  // svt_process_batch_static
         if (flags & SVT_BATCH_GRAPH) return SVT_ERR_ARG;  // instantiating a graph allocates
         if (svt_batch_workspace(word_cap, road_cap, combo_cap, &t) > SVT_STATIC_WORK_BYTES)

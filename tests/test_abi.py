@@ -192,3 +192,25 @@ def test_static_workspace_limit_and_host_rejections():
     assert fn(*nobank) == L.SVT_ERR_ARG
     # a negative workspace size stays an argument error on the workspace entry point
     assert lib.svt_process_batch(*args[:18], fake, -2, 0, None) == L.SVT_ERR_ARG
+
+
+def test_schedule_zero_is_chosen_from_the_word_capacity():
+    """Schedule 0: the one-pass kernel up to 2^19 words of capacity, pre-pass + tiles above;
+    an explicit schedule is kept; the workspace follows the chosen schedule."""
+    small = L.svt_tune_for_batch(None, 1 << 19)
+    large = L.svt_tune_for_batch(None, (1 << 19) + 1)
+    assert small.schedule == L.SVT_SCHEDULE_ONEPASS and large.schedule == L.SVT_SCHEDULE_TILES
+    assert L.svt_tune_for_batch(L.make_tune(schedule=L.SVT_SCHEDULE_TILES), 100).schedule == \
+        L.SVT_SCHEDULE_TILES
+    assert L.svt_tune_for_batch(L.make_tune(schedule=L.SVT_SCHEDULE_ONEPASS), 1 << 30).schedule == \
+        L.SVT_SCHEDULE_ONEPASS
+    assert (small.tile_combos, small.chunk_roads, small.wg_size, small.wgs_per_cu) == \
+        (4096, 64, 256, 3)
+    # schedule 0 must suit the one-pass kernel too: at most 3 workgroups per CU
+    with pytest.raises(L.SvtError):
+        L.svt_tune_for_batch(L.make_tune(wgs_per_cu=4), 1 << 25)
+    assert L.svt_tune_for_batch(L.make_tune(wgs_per_cu=4, schedule=L.SVT_SCHEDULE_TILES),
+                                1 << 25).wgs_per_cu == 4
+    for cap in (1000, 1 << 19, 1 << 22):
+        assert L.svt_batch_workspace(cap, cap // 5, 4 * cap, None) == \
+            L.svt_batch_workspace(cap, cap // 5, 4 * cap, L.svt_tune_for_batch(None, cap))
