@@ -448,6 +448,8 @@ def measure_small(sample, bank, cut, reps, ora_s):
     words = P.words_tensor(sample.words)
     runner = P.BatchRunner(gcfg, dbank, nw, nr, nc, kept_cap=0, graph=True, with_c=False)
     runner.load(words)
+    from paper_1312_0917_amd import tune as T
+    modes = T.pick_launch_mode(runner)
     for _ in range(5):
         runner.run()
     torch.cuda.synchronize()
@@ -475,6 +477,7 @@ def measure_small(sample, bank, cut, reps, ora_s):
         t.append(time.perf_counter() - t0)
     with_io = float(np.median(t[5:]))
     L.svt_release_graphs()
+    small_graph = runner.graph
     del runner
     pr = P.PlainRunner(gcfg, dbank, with_c=False, want_kept=False)
     for _ in range(5):
@@ -491,7 +494,9 @@ def measure_small(sample, bank, cut, reps, ora_s):
     return dict(workload=f"c1: {sample.n_events} events, {nr} roads, {nw} hit words, "
                          f"{nc} combinations",
                 reps=reps, statistic="median",
-                batched=dict(us_per_pass=us(resident), value=nc / resident),
+                batched=dict(us_per_pass=us(resident), value=nc / resident,
+                             launch="graph replay" if small_graph else "direct launches",
+                             launch_modes_ms_per_pass=modes),
                 batched_with_io=dict(us_per_pass=us(with_io), value=nc / with_io,
                                      io="words in from page-locked memory, the 6 per-road "
                                         "best-track arrays out"),
@@ -633,10 +638,16 @@ def main():
     # the schedule the library runs for this batch (a zero schedule is chosen per capacity)
     tune = L.svt_tune_for_batch(tune, n_words)
 
-    # ---- batched path: resident buffers, graph replay -------------------------------------
+    # ---- batched path: resident buffers; graph replays or direct launches, whichever is faster
     runner = P.BatchRunner(gcfg, dbank, n_words, n_roads, n_combos, kept_cap=0, tune=tune,
                            graph=not args.no_graph, with_c=False)
     runner.load(words)
+    launch_modes = None
+    if not args.no_graph:
+        from paper_1312_0917_amd import tune as T
+        log("launch mode: graph replays against direct launches")
+        launch_modes = T.pick_launch_mode(runner)
+        launch_modes["statistic"] = "median of 30 samples of 5 passes each"
     log("batched warmup")
     for _ in range(W):
         runner.run()
@@ -652,6 +663,7 @@ def main():
     t1 = time.perf_counter()
     batch_s = (t1 - t0) / K
     value = n_combos / batch_s
+    runner_graph = runner.graph
 
     # ---- the dominant kernel alone: HIP events on the runner's stream around its launch ----
     log("kernel timing")
@@ -671,7 +683,7 @@ def main():
             extra = []
             for _ in range(n_fl - 1):
                 r = P.BatchRunner(gcfg, dbank, n_words, n_roads, n_combos, kept_cap=0, tune=tune,
-                                  graph=not args.no_graph, with_c=False)
+                                  graph=runner_graph, with_c=False)
                 r.load(words)
                 extra.append(r)
             group = [runner] + extra
@@ -702,7 +714,7 @@ def main():
         ev_tune = L.svt_tune_resolve(L.make_tune(tune.tile_combos, tune.chunk_roads, tune.wg_size,
                                                  4, 1))
         er = P.BatchRunner(gcfg, dbank, n_words, n_roads, n_combos, kept_cap=0, tune=ev_tune,
-                           graph=not args.no_graph, with_c=False)
+                           graph=runner_graph, with_c=False)
         er.load(words)
         for _ in range(W):
             er.run()
@@ -724,7 +736,7 @@ def main():
         log("kept-only mode")
         L.svt_release_graphs()
         kept_only = measure_kept_only(gcfg, dbank, words, n_words, n_roads, n_combos, tune, K, W,
-                                      not args.no_graph)
+                                      runner_graph)
 
     # ---- plain path: one launch per stage, host syncs to size each stage ------------------
     plain = None
@@ -788,7 +800,8 @@ def main():
                              f"({n_combos / max(n_events, 1):.0f} per event)",
                     events=n_events, roads=n_roads, words=n_words, combinations=n_combos,
                     chi2_cut=cut, path="svt_process_batch (%s)" % (
-                        "direct launches" if args.no_graph else "graph replay"),
+                        "graph replay" if runner_graph else "direct launches"),
+                    launch_modes_ms_per_pass=launch_modes,
                     tune=tune_dict(tune), autotune=tuned, device=dev_name),
         roofline=roofline, int_ops=int_ops(n_combos, k_ms, tune), cpu_baseline=cpu,
         small_batch=small_res, kept_only=kept_only,

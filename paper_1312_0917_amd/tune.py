@@ -144,3 +144,30 @@ def autotune(words: torch.Tensor, bank: torch.Tensor, cfg: L.svt_config, n_roads
         json.dump(data, open(tmp, "w"), indent=1)
         os.replace(tmp, cache_path)
     return res
+
+
+def pick_launch_mode(runner: P.BatchRunner, samples: int = 30, per_sample: int = 5,
+                     warmup: int = 3):
+    """Time one batch runner with graph replays and with direct launches (the same statistic as
+    autotune) and leave it in the faster mode.  Returns {"graph": ms, "direct": ms}.
+
+    The pass is the same kernels either way; on ROCm a replayed graph costs several
+    microseconds more per pass than launching its kernels directly, which matters for batches
+    whose pass takes tens of microseconds."""
+    times = {}
+    for graph in (True, False):
+        runner.graph = graph
+        for _ in range(warmup):
+            runner.run()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(samples):
+            t0 = time.perf_counter()
+            for _ in range(per_sample):
+                runner.run()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) / per_sample * 1e3)
+        times["graph" if graph else "direct"] = round(float(np.median(ts)), 5)
+    runner.graph = times["graph"] <= times["direct"]
+    return times
+
