@@ -46,7 +46,7 @@ CSRC = os.path.join(ROOT, "paper_1312_0917_amd", "csrc")
 # sources each timed kernel is compiled from: recorded HBM counters are valid while these match
 KERNEL_SOURCES = {
     "k_fused": ["svt_fused.hip", "svt_fit.h", "svt_common.h"],
-    "k_onepass": ["svt_onepass.hip", "svt_fit.h", "svt_common.h"],
+    "k_onepass": ["svt_onepass.hip", "svt_fit.h", "svt_lookback.h", "svt_common.h"],
     "k_fit_events": ["svt_events.hip", "svt_common.h"],
 }
 
