@@ -206,12 +206,16 @@ svt_status svt_select(const svt_config *cfg, const svt_roads *roads, int64_t n_r
                       hipStream_t stream);
 
 /* The whole path in one pass (sections II and II-A: unpack, combine, fit, plus the chi-square
- * selection).  A single-pass pre-pass reads every word once and writes the road table, the
- * layer-grouped coordinates and each road's combination range (one kernel: decoupled look-back
- * over blocks of 2048 words).  A persistent fused kernel then takes tiles of tile_combos
- * consecutive combinations, stages the roads' hits and constants in LDS, fits every combination
- * with integer VALU arithmetic and writes the same records, accept flags, road table and best
- * tracks as stages 1-4 (bit for bit).  The word count is read on the device from *d_n_words, so
+ * selection), writing the same records, accept flags, road table and best tracks as stages 1-4
+ * (bit for bit) with one of two schedules (svt_tune.schedule; 0 chooses from word_cap, see
+ * svt_tune_for_batch):
+ *   - SVT_SCHEDULE_ONEPASS: one persistent kernel unpacks, combines, fits and selects units of
+ *     1024 words, each workgroup holding its unit's roads in LDS (plus a reset launch);
+ *   - SVT_SCHEDULE_TILES: a single-pass pre-pass reads every word once and writes the road
+ *     table, the layer-grouped coordinates and each road's combination range (decoupled
+ *     look-back over blocks of 2048 words); a persistent fused kernel then takes tiles of
+ *     tile_combos consecutive combinations, stages the roads' hits and constants in LDS and fits
+ *     every combination with integer VALU arithmetic; a last launch writes the best tracks.  The word count is read on the device from *d_n_words, so
  * a captured graph can be replayed for any batch up to word_cap (at most 2^31 - 1 words;
  * larger capacities are SVT_ERR_ARG, and svt_batch_workspace returns -1 for them).
  * flags: SVT_BATCH_GRAPH
