@@ -52,11 +52,17 @@ KERNEL_SOURCES = {
 
 
 def kernel_source_digest(kernel):
+    """SHA-1 of the kernel's source files with comments and blank lines removed (a comment
+    edit does not change the kernel the counters were taken on)."""
     h = hashlib.sha1()
     for f in KERNEL_SOURCES[kernel]:
         path = os.path.join(CSRC, f)
         if os.path.exists(path):
-            h.update(open(path, "rb").read())
+            text = open(path).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", "", text)
+            code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+            h.update(code.encode())
     return h.hexdigest()[:16]
 
 

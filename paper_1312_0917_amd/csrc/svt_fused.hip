@@ -8,11 +8,13 @@
 // q = qh * 2^s + ql with 0 <= ql < 2^s: ql seeds the accumulator, so the sum stays inside
 // int32, and
 //     floor((S + q) / 2^s) = qh + floor((S + ql) / 2^s)       (exact for every integer S).
+// A chunk whose every road's constant set has small enough bounds (narrow_ok) takes the narrow
+// form instead: the whole offset seeds the accumulator and chi-square is summed in 32 bits.
 //
 // Work distribution: combinations are numbered globally (road-major, combo_begin from the
 // pre-pass); each workgroup of a persistent grid walks tiles of tile_combos consecutive
 // combinations taken from an atomic counter, and stages the roads of a tile in LDS in chunks
-// of up to 64 roads.  Wave 0 of the workgroup is a loader: while the other waves fit chunk i
+// of up to chunk_roads (16, 32 or 64) roads.  Wave 0 of the workgroup is a loader: while the other waves fit chunk i
 // from one LDS buffer, it stages chunk i+1 in the other (road table, constants, one coalesced
 // copy of the chunk's layer-grouped coordinates, pair tables, group-to-road map), so global
 // latency hides behind arithmetic.  Compute lanes fit 4 consecutive combinations each and
