@@ -63,3 +63,32 @@ def test_static_workspace_matches_workspace_entry_point(two_batches, bank, sched
                 assert a[k].shape == b[k].shape and np.array_equal(a[k], b[k]), f"{where}: {k}"
             else:
                 assert a[k] == b[k], f"{where}: {k}"
+
+
+@pytest.mark.parametrize("schedule", [L.SVT_SCHEDULE_ONEPASS, L.SVT_SCHEDULE_TILES])
+def test_static_entry_point_inside_a_callers_graph(two_batches, bank, schedule):
+    """The case the entry point is for: a caller captures svt_process_batch_static into a graph
+    of its own (no allocation can happen under capture) and replays it.  Between replays the
+    caller loads another batch (words and device word count, eager work on its own stream); every
+    replay must equal the oracle for the batch then loaded."""
+    _, words0, ref0 = two_batches[0]
+    wc, rc, cc = caps_for(words0, ref0)
+    d_bank = P.device_bank(bank.f, bank.q)
+    r = P.BatchRunner(gpu_cfg(CFG), d_bank, wc, rc, cc, kept_cap=cc,
+                      tune=L.make_tune(schedule=schedule), graph=False, static_workspace=True)
+    r.load(P.words_tensor(words0), len(words0)).run()  # eager first call: the device's address
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=r.stream):
+        L.check(r._call(r.words, 0, r.stream), "svt_process_batch_static under capture")
+    torch.cuda.synchronize()
+    order = [two_batches[1], two_batches[0], two_batches[1]]
+    for i, (name, words, ref) in enumerate(order):
+        print(f"[no-alloc] replay {i}: {name}, schedule={schedule}", flush=True)
+        r.load(P.words_tensor(words), len(words))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(r.stream):
+            g.replay()
+        torch.cuda.synchronize()
+        compare(ref, outputs(r), BATCH_KEYS, f"replay {i} {name} schedule={schedule}")
+    del g
