@@ -63,8 +63,9 @@ struct BatchWs {
     int64_t *n_events;  // events of the batch
     int32_t *efr;       // first road of every event
     int64_t events_cap;
-    int64_t *status;    // look-back status words, 2 per word block
-    int64_t nb;
+    int64_t *status;    // look-back status words
+    int64_t status_words;
+    int64_t nb;         // one-pass units of the capacity
     int32_t *tfr;
     int64_t tiles_cap;
     int64_t *kb;
@@ -79,9 +80,12 @@ BatchWs carve_batch(Carver &c, int64_t word_cap, int64_t road_cap, int64_t combo
     w.n_events = c.take<int64_t>(2);
     w.events_cap = road_cap > 0 ? road_cap : 1;  // every event holds at least one road
     w.efr = c.take<int32_t>(w.events_cap);
-    // status words for the smaller of the two word-block sizes (the one-pass units)
+    // status words for the one-pass units or for the pre-pass blocks and their groups
     w.nb = ceil_div(word_cap > 0 ? word_cap : 1, kOnepassUnitWords);
-    w.status = c.take<int64_t>(2 * w.nb);
+    const int64_t pre = prepass_status_words(ceil_div(word_cap > 0 ? word_cap : 1,
+                                                      kPrepassBlockWords));
+    w.status_words = 2 * w.nb > pre ? 2 * w.nb : pre;
+    w.status = c.take<int64_t>(w.status_words);
     // tile marks at the smaller of the tile and the kept block (the one-pass kernel marks
     // kept blocks)
     w.tiles_cap = ceil_div(combo_cap > 0 ? combo_cap : 1, tile < kKeptBlock ? tile : kKeptBlock) + 1;
@@ -409,6 +413,7 @@ static svt_status batch_sequence(const FusedLaunch &f, const BatchWs &w, int64_t
     if (f.tune.schedule == SVT_SCHEDULE_ONEPASS) {
         // reset, the one-pass kernel, and with a kept list its scan and compaction
         p.nb_cap = w.nb;
+        p.status_words = 2 * w.nb;
         SVT_TRY(launch_batch_reset(p, w.nw_copy, d_n_kept, d_n_kept ? w.kb : nullptr,
                                    d_n_kept ? w.kbn : 0, stream));
         OnepassLaunch o{};
@@ -453,6 +458,7 @@ static svt_status batch_sequence(const FusedLaunch &f, const BatchWs &w, int64_t
     }
     // (the kept-list block counts are cleared with the rest: the fused kernel adds to them)
     p.nb_cap = ceil_div(word_cap > 0 ? word_cap : 1, kPrepassBlockWords);
+    p.status_words = prepass_status_words(p.nb_cap);
     SVT_TRY(launch_batch_reset(p, w.nw_copy, d_n_kept, d_n_kept ? w.kb : nullptr,
                                d_n_kept ? w.kbn : 0, stream));
     p.nw = nw_dev;

@@ -13,6 +13,11 @@ constexpr int kSegThreads = 256;          // threads of the word-segmentation ke
 constexpr int kSegWordsPerThread = 16;
 constexpr int kSegBlockWords = kSegThreads * kSegWordsPerThread;  // 4096 words per block
 constexpr int kPrepassBlockWords = 2048;  // words per block of the batched single-pass pre-pass
+constexpr int kLookGroup = 64;            // pre-pass blocks per group of its two-level look-back
+// look-back status words of the pre-pass: two per block, then two per group of kLookGroup blocks
+inline int64_t prepass_status_words(int64_t nb_cap) {
+    return 2 * nb_cap + 2 * ((nb_cap + kLookGroup - 1) / kLookGroup);
+}
 constexpr int kOnepassUnitWords = 1024;   // words per unit of the one-pass kernel
 constexpr int kRoadBlock = 256;           // roads per block in road-table kernels
 constexpr int kKeptBlock = 4096;          // combinations per block of the kept-list compaction
@@ -248,17 +253,17 @@ struct PrepassLaunch {
     int64_t combo_cap;
     int64_t *d_n_roads;
     int64_t *d_n_combos;
-    int64_t *status;           // 2 * nb_cap look-back status words
+    int64_t *status;           // look-back status words (prepass_status_words(nb_cap))
     int64_t nb_cap;            // ceil(word_cap / kPrepassBlockWords)
+    int64_t status_words;      // status words the reset clears
     uint32_t *tickets;         // [0] fused-kernel tiles, [1] pre-pass blocks
     uint64_t *err;
     int32_t *event_first_road; // first road of every event (event_cap entries)
     int64_t event_cap;
     int64_t *d_n_events;
 };
-// Clears the error word, both tickets, *d_n_kept (nullable), the status words in use (one pair
-// per block_words words of the batch) and zero[0 .. n_zero) (the kept-list block counts;
-// nullable).
+// Clears the error word, both tickets, *d_n_kept (nullable), status[0 .. status_words) and
+// zero[0 .. n_zero) (the kept-list block counts; nullable).
 hipError_t launch_batch_reset(const PrepassLaunch &p, int64_t *nw_copy, int64_t *d_n_kept,
                               int64_t *zero, int64_t n_zero, hipStream_t s);
 hipError_t launch_prepass(const PrepassLaunch &p, hipStream_t s);

@@ -14,11 +14,19 @@
 // error (some layer must then hold more than max_hits hits).
 //
 // Everything a block needs from its own words (road list, hits per layer, combinations,
-// grouped coordinates) is computed before it looks back, so the only wait is one look-back.
-// Two 64-bit status words per block carry the running counts -- roads and events packed in one
-// (31 bits each: a batch holds fewer than 2^31 words), combinations in the other: the top two
-// bits say "aggregate of this block" or "inclusive prefix up to this block", the rest hold the
-// value.  The status words are cleared by the batch-reset kernel before every pass.
+// grouped coordinates, even their coalesced store) is done before it looks back, so the only
+// wait is one look-back.  Two 64-bit status words per block carry the running counts -- roads
+// and events packed in one (31 bits each: a batch holds fewer than 2^31 words), combinations in
+// the other: the top two bits say "aggregate" or "inclusive prefix", the rest hold the value.
+// The look-back has two levels (look_back_grouped): a block sums the aggregates of the blocks
+// before it in its group of 64 and the values of the groups before that, which the groups'
+// last blocks publish.  The status words are cleared by the batch-reset kernel before every
+// pass.
+//
+// LDS per block stays near 21 KB, so that seven blocks fit on a compute unit: the grouped
+// coordinates go into the high halves of the staged words of their own road, the road list
+// holds 16-bit starts, and a road's event index comes from the same block scan as its first
+// combination.
 //
 // Blocks are numbered by their index in the grid, with no ticket: every block fetching an
 // ordered ticket from one counter at the start serialises on that counter (about 12 ns per
@@ -28,7 +36,7 @@
 // wait forever on one that has not been scheduled, and the wait stays bounded.
 #include <cstdlib>
 
-#include "svt_lookback.h"
+#include "svt_lookback_block.h"
 
 namespace svt {
 namespace {
@@ -62,20 +70,28 @@ struct PArgs {
     int64_t *d_n_events;
 };
 
-// Per owned road, in LDS: s_road[rl] = first local word (12 bits) | events started in the block
-// up to that word (12 bits) << 12 | the word starts an event << 24; s_info[rl] = hits per layer
-// (4 bits each) | too-many-hits << 20 | no-constant-set << 21.
-constexpr uint32_t kInfoOver = 1u << 20;
-constexpr uint32_t kInfoSet = 1u << 21;
+// Per owned road, in LDS: s_road[rl] = first local word (12 bits) | the word starts an event
+// << 12; s_info[rl] = hits per layer (4 bits each) | road tag << 20 | too-many-hits << 28 |
+// no-constant-set << 29.  The road that starts at s_road[rl] ends where road rl + 1 starts, the
+// last one at s_tail_end.
+constexpr uint32_t kInfoOver = 1u << 28;
+constexpr uint32_t kInfoSet = 1u << 29;
+
+__device__ inline int road_end(const uint16_t *s_road, int rl, int nroads, int tail_end) {
+    return rl + 1 < nroads ? (s_road[rl + 1] & 0xFFF) : tail_end;
+}
 
 __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
-    __shared__ __align__(16) uint32_t sw[kOff + kPB + kTail];  // word base + j at sw[kOff + j]
-    __shared__ int16_t sc[kPB + kTail];   // grouped coordinates, same local positions
-    __shared__ uint32_t s_road[kPB + 1];  // [n_owned] holds the end of the last owned road
+    // sw[kOff + j] = word base + j.  Once a road's hits are counted, the high halves of its own
+    // words receive its coordinates grouped by layer (the low halves, coordinate and layer,
+    // stay as read): 16-bit store k of the road goes to the high half of its word k.
+    __shared__ __align__(16) uint32_t sw[kOff + kPB + kTail];
+    __shared__ uint16_t s_road[kPB];
     __shared__ uint32_t s_info[kPB];
     __shared__ int64_t tmp[kPT / kWaveSize + 1];
-    __shared__ int64_t s_pre[3];
+    __shared__ GroupLookShared s_look;
     __shared__ int32_t s_tail_end;
+    uint16_t *sh16 = reinterpret_cast<uint16_t *>(sw);
 
     const int tid = threadIdx.x;
     const int64_t n = load_size(a.nw);
@@ -157,33 +173,31 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
     int64_t tre;  // roads and events of the block, scanned together (each at most 2048)
     const int64_t rel0 = block_excl_scan<int64_t, kPT>(static_cast<int64_t>(nr) |
                                                        (static_cast<int64_t>(ne) << 32), tmp, tre);
-    const int rl0 = static_cast<int>(rel0 & 0xFFFFFFFF), el0 = static_cast<int>(rel0 >> 32);
     const int64_t tr = tre & 0xFFFFFFFF, te = tre >> 32;
     const int nroads = static_cast<int>(tr);
 
-    // ---- list of owned roads ------------------------------------------------------------------
+    // ---- list of owned roads (every event start is a road start: the tags hold both) --------
     {
-        int rl = rl0;
-        int ev = el0;  // events started in the block up to the current word
+        int rl = static_cast<int>(rel0 & 0xFFFFFFFF);
 #pragma unroll
-        for (int e = 0; e < kPW; ++e) {
-            ev += (emask >> e) & 1u;
-            if ((rmask >> e) & 1u) s_road[rl++] = static_cast<uint32_t>(j0 + e) |
-                                                  (static_cast<uint32_t>(ev) << 12) |
-                                                  (((emask >> e) & 1u) << 24);
-        }
-        if (tid == 0) s_road[nroads] = static_cast<uint32_t>(s_tail_end);
+        for (int e = 0; e < kPW; ++e)
+            if ((rmask >> e) & 1u)
+                s_road[rl++] = static_cast<uint16_t>((j0 + e) | (((emask >> e) & 1u) << 12));
     }
     __syncthreads();
+    const int tail_end = s_tail_end;
 
     // ---- one road per thread: hits per layer, checks, combinations --------------------------
+    // Counts and, below, write offsets per layer are packed 6 bits a layer in one word: a road
+    // that is not too long has at most 40 hits.
     const int max_len = a.cfg.n_layers * a.cfg.max_hits;
     int64_t csum = 0;
     for (int rl = tid; rl < nroads; rl += kPT) {
         const int j = s_road[rl] & 0xFFF;
-        const int len = static_cast<int>(s_road[rl + 1] & 0xFFF) - j;
+        const int len = road_end(s_road, rl, nroads, tail_end) - j;
+        const uint32_t w0 = sw[kOff + j];
         bool over = len > max_len;
-        uint64_t cnt = 0;  // 8 bits per layer
+        uint32_t cnt = 0;
         if (!over) {
             for (int i0 = 0; i0 < len; i0 += 8) {
                 uint32_t x[8];
@@ -192,20 +206,21 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const uint32_t l = w_layer(x[u]);  // 7 for the padding
-                    if (l < SVT_N_LAYERS) cnt += 1ull << (8 * l);
+                    if (l < SVT_N_LAYERS) cnt += 1u << (6 * l);
                 }
             }
         }
         uint32_t packed = 0;
 #pragma unroll
         for (int l = 0; l < SVT_N_LAYERS; ++l) {
-            const uint32_t c = static_cast<uint32_t>((cnt >> (8 * l)) & 0xFF);
+            const uint32_t c = (cnt >> (6 * l)) & 0x3F;
             over |= c > static_cast<uint32_t>(a.cfg.max_hits);
             packed |= (c & 0xFu) << (4 * l);
         }
         if (!over) csum += combos_of(packed);
-        const bool noset = w_rtag(sw[kOff + j]) >= static_cast<uint32_t>(a.cfg.n_sets);
-        s_info[rl] = packed | (over ? kInfoOver : 0u) | (noset ? kInfoSet : 0u);
+        const bool noset = w_rtag(w0) >= static_cast<uint32_t>(a.cfg.n_sets);
+        s_info[rl] = packed | (w_rtag(w0) << 20) | (over ? kInfoOver : 0u) |
+                     (noset ? kInfoSet : 0u);
     }
     const int64_t tc = block_sum<int64_t, kPT>(csum, tmp);  // (its barrier publishes s_info)
     const uint64_t agg0 = static_cast<uint64_t>(tr) | (static_cast<uint64_t>(te) << 31);
@@ -218,12 +233,12 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
         const uint32_t info = s_info[rl];
         if (info & kInfoOver) continue;
         const int j = s_road[rl] & 0xFFF;
-        const int len = static_cast<int>(s_road[rl + 1] & 0xFFF) - j;
-        uint32_t off[SVT_N_LAYERS];
+        const int len = road_end(s_road, rl, nroads, tail_end) - j;
+        uint32_t off = 0;  // next write position per layer, 6 bits a layer
         uint32_t run = 0;
 #pragma unroll
         for (int l = 0; l < SVT_N_LAYERS; ++l) {
-            off[l] = run;
+            off |= run << (6 * l);
             run += nh_of(info, l);
         }
         for (int i0 = 0; i0 < len; i0 += 8) {
@@ -234,55 +249,60 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
             for (int u = 0; u < 8; ++u) {
                 const uint32_t l = w_layer(x[u]);
                 if (l >= SVT_N_LAYERS) continue;
-                uint32_t o = 0;
-#pragma unroll
-                for (int k = 0; k < SVT_N_LAYERS; ++k)
-                    if (static_cast<uint32_t>(k) == l) { o = off[k]; off[k] = o + 1; }
-                sc[j + o] = static_cast<int16_t>(w_coord(x[u]));
+                const uint32_t o = (off >> (6 * l)) & 0x3F;
+                off += 1u << (6 * l);
+                sh16[2 * (kOff + j + static_cast<int>(o)) + 1] = static_cast<uint16_t>(x[u]);
             }
         }
     }
+    __syncthreads();
+
+    // ---- grouped coordinates of the owned roads: contiguous, coalesced (no prefix needed) ---
+    if (nroads > 0) {
+        const int lo = s_road[0] & 0xFFF;
+        for (int j = lo + tid; j < tail_end; j += kPT)
+            a.coords[base + j] = static_cast<int16_t>(static_cast<int32_t>(
+                                     static_cast<uint32_t>(sh16[2 * (kOff + j) + 1]) << 19) >> 19);
+    }
 
     // ---- running counts of the blocks before this one (roads and events share a word: both
-    // stay below 2^31) ---------------------------------------------------------------------------
-    if (tid < kWaveSize) {
-        uint64_t p0, p1;
-        look_back2<kPB>(lc, b, agg0, agg1, p0, p1);
-        if (tid == 0) {
-            s_pre[0] = static_cast<int64_t>(p0 & 0x7FFFFFFFull);
-            s_pre[1] = static_cast<int64_t>(p0 >> 31);
-            s_pre[2] = static_cast<int64_t>(p1);
-        }
-    }
-    __syncthreads();
-    const int64_t R0 = s_pre[0], E0 = s_pre[1];
+    // stay below 2^31) --------------------------------------------------------------------------
+    uint64_t p0, p1;
+    look_back_grouped<kPB>(lc, b, agg0, agg1, s_look, p0, p1);
+    const int64_t R0 = static_cast<int64_t>(p0 & 0x7FFFFFFFull);
+    const int64_t E0 = static_cast<int64_t>(p0 >> 31);
 
-    // ---- road table, combo_begin (scan over the road list), tiles, best keys ----------------
+    // ---- road table, combo_begin and event index (one scan over the road list), tiles, best
+    // keys ---------------------------------------------------------------------------------------
     {
-        int64_t carry = s_pre[2];
+        constexpr int kEvShift = 48;  // a block's combinations stay far below 2^48
+        int64_t carry = static_cast<int64_t>(p1);
+        int64_t ecarry = E0 - 1;  // the event of the block's first word, before its own starts
         const int64_t T = a.tile_combos;
         uint64_t *keys = reinterpret_cast<uint64_t *>(a.best.chi2);
         for (int q0 = 0; q0 < nroads; q0 += kPT) {
             const int rl = q0 + tid;
             const bool mine = rl < nroads;
             const uint32_t info = mine ? s_info[rl] : kInfoOver;
+            const uint32_t rd = mine ? s_road[rl] : 0u;
+            const int64_t evs = (rd >> 12) & 1u;
             const int64_t c = (info & kInfoOver) ? 0 : combos_of(info);
             int64_t tot;
-            const int64_t cb = carry + block_excl_scan<int64_t, kPT>(c, tmp, tot);
-            carry += tot;
+            const int64_t sc = block_excl_scan<int64_t, kPT>(c | (evs << kEvShift), tmp, tot);
+            const int64_t cb = carry + (sc & ((1ll << kEvShift) - 1));
+            const int64_t ev = ecarry + (sc >> kEvShift) + evs;
+            carry += tot & ((1ll << kEvShift) - 1);
+            ecarry += tot >> kEvShift;
             if (!mine) continue;
             const int64_t r = R0 + rl;
             if (info & kInfoOver) report(a.err, SVT_ERRCLASS_HITS, static_cast<uint64_t>(r));
             if (info & kInfoSet) report(a.err, SVT_ERRCLASS_SET, static_cast<uint64_t>(r));
             if (r >= a.road_cap) continue;
-            const uint32_t rd = s_road[rl];
-            const int j = rd & 0xFFF;
-            const int64_t ev = E0 + ((rd >> 12) & 0xFFF) - 1;
             a.roads.event[r] = static_cast<int32_t>(ev);
-            if (a.event_first_road && ((rd >> 24) & 1u) && ev < a.event_cap)
+            if (a.event_first_road && evs && ev < a.event_cap)
                 a.event_first_road[ev] = static_cast<int32_t>(r);
-            a.roads.set[r] = static_cast<int32_t>(w_rtag(sw[kOff + j]));
-            a.roads.hit_begin[r] = base + j;
+            a.roads.set[r] = static_cast<int32_t>((info >> 20) & 0xFFu);
+            a.roads.hit_begin[r] = base + (rd & 0xFFF);
             a.roads.nhits[r] = info & 0xFFFFFu;
             a.roads.ncombo[r] = static_cast<int32_t>(c);
             a.roads.combo_begin[r] = cb;
@@ -295,14 +315,9 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
         }
     }
 
-    // ---- grouped coordinates of the owned roads: contiguous, coalesced ----------------------
-    if (nroads > 0) {
-        const int lo = s_road[0] & 0xFFF, hi = s_road[nroads] & 0xFFF;
-        for (int j = lo + tid; j < hi; j += kPT) a.coords[base + j] = sc[j];
-    }
     if (b == nb - 1 && tid == 0) {
         const int64_t n_roads = R0 + tr;
-        const int64_t n_combos = s_pre[2] + tc;
+        const int64_t n_combos = static_cast<int64_t>(p1) + tc;
         *a.d_n_roads = n_roads;
         *a.d_n_combos = n_combos;
         if (a.d_n_events) *a.d_n_events = E0 + te;
@@ -312,12 +327,12 @@ __global__ __launch_bounds__(kPT) void k_prepass(PArgs a) {
 }
 
 // Clears the error word, the work tickets (the fused kernel's tile counter is the first), the
-// kept count, all nb_cap look-back status words and, when given, zero[0 .. n_zero) (the kept
+// kept count, the look-back status words in use and, when given, zero[0 .. n_zero) (the kept
 // list's per-block counts, which the fused kernel adds to); copies the word count into
 // *nw_copy, where the pass's later kernels read it (the count may live in page-locked host
 // memory, and one read of it beats one per wave across the bus).
 __global__ void k_batch_reset(uint64_t *err, uint32_t *tickets, int64_t *d_n_kept,
-                              int64_t *status, int64_t nb_cap, Sizes nw, int64_t *nw_copy,
+                              int64_t *status, int64_t n_status, Sizes nw, int64_t *nw_copy,
                               int64_t *zero, int64_t n_zero) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *err = SVT_NO_ERROR;
@@ -326,10 +341,7 @@ __global__ void k_batch_reset(uint64_t *err, uint32_t *tickets, int64_t *d_n_kep
         if (d_n_kept) *d_n_kept = 0;
         *nw_copy = nw.dev ? *nw.dev : nw.host;  // the one read of a (possibly host-side) count
     }
-    for (int64_t i = gtid(); i < nb_cap; i += gstride()) {
-        status[i] = 0;
-        status[nb_cap + i] = 0;
-    }
+    for (int64_t i = gtid(); i < n_status; i += gstride()) status[i] = 0;
     if (zero)
         for (int64_t i = gtid(); i < n_zero; i += gstride()) zero[i] = 0;
 }
@@ -367,12 +379,12 @@ hipError_t launch_prepass(const PrepassLaunch &p, hipStream_t s) {
 
 hipError_t launch_batch_reset(const PrepassLaunch &p, int64_t *nw_copy, int64_t *d_n_kept,
                               int64_t *zero, int64_t n_zero, hipStream_t s) {
-    const int64_t items = zero && n_zero > p.nb_cap ? n_zero : p.nb_cap;
+    const int64_t items = zero && n_zero > p.status_words ? n_zero : p.status_words;
     int64_t blocks = (items + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(k_batch_reset, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
-                       p.err, p.tickets, d_n_kept, p.status, p.nb_cap, p.nw, nw_copy, zero,
+                       p.err, p.tickets, d_n_kept, p.status, p.status_words, p.nw, nw_copy, zero,
                        zero ? n_zero : 0);
     return hipGetLastError();
 }

@@ -36,17 +36,39 @@ def forced_fallback():
     L.svt_release_graphs()
 
 
+# both look-backs: the one-pass kernel's (units of 1024 words, one wave) and the pre-pass's
+# (blocks of 2048 words in groups of 64)
+SCHEDULES = {"onepass": L.SVT_SCHEDULE_ONEPASS, "prepass": L.SVT_SCHEDULE_TILES}
+
+
+@pytest.mark.parametrize("schedule", list(SCHEDULES))
 @pytest.mark.parametrize("config,n_events", [("c2", 150), ("c3", 300)])
-def test_forced_fallback_matches_oracle(bank, forced_fallback, config, n_events):
+def test_forced_fallback_matches_oracle(bank, forced_fallback, config, n_events, schedule):
     s = synth.make_sample(config, bank=bank, n_events=n_events)
     assert len(s.words) > 40 * 2048, "several dozen pre-pass blocks"
     cfg = oracle.make_config(chi2_cut=synth.config_chi2_cut(config))
     ref = oracle.run(s.words, bank.f, bank.q, cfg)
-    got, _ = run_batch(s.words, bank.f, bank.q, cfg, ref=ref, graph=False)
-    compare(ref, got, BATCH_KEYS, f"forced fallback {config}")
+    got, _ = run_batch(s.words, bank.f, bank.q, cfg, ref=ref, graph=False,
+                       tune=L.make_tune(schedule=SCHEDULES[schedule]))
+    compare(ref, got, BATCH_KEYS, f"forced fallback {config} {schedule}")
 
 
-def test_forced_fallback_keeps_required_sizes_of_bad_input(bank, forced_fallback):
+@pytest.mark.parametrize("schedule", list(SCHEDULES))
+def test_forced_fallback_across_groups(bank, forced_fallback, schedule):
+    """Pre-pass blocks in groups past the first also sum group values (level 2 of its
+    look-back); with the wait bound at zero they compute missing group values from the blocks'
+    words."""
+    s = synth.make_sample("c2", bank=bank, n_events=1000)
+    assert len(s.words) > 4 * 64 * 2048, "five groups of 64 pre-pass blocks"
+    cfg = oracle.make_config(chi2_cut=synth.config_chi2_cut("c2"))
+    ref = oracle.run(s.words, bank.f, bank.q, cfg)
+    got, _ = run_batch(s.words, bank.f, bank.q, cfg, ref=ref, graph=False,
+                       tune=L.make_tune(schedule=SCHEDULES[schedule]))
+    compare(ref, got, BATCH_KEYS, f"forced fallback across look-back groups, {schedule}")
+
+
+@pytest.mark.parametrize("schedule", list(SCHEDULES))
+def test_forced_fallback_keeps_required_sizes_of_bad_input(bank, forced_fallback, schedule):
     """Roads with too many hits on a layer, and roads longer than any legal one, spread over
     many blocks: no combinations for them, every size as the oracle counts it."""
     rng = np.random.default_rng(11)
@@ -73,7 +95,8 @@ def test_forced_fallback_keeps_required_sizes_of_bad_input(bank, forced_fallback
     for mode, ticks in (("own", "20000"), ("forced", "0")):
         os.environ[HOOK] = ticks
         runner = P.BatchRunner(gpu_cfg(CFG), P.device_bank(bank.f, bank.q), len(words),
-                               nr + 8, 64 * len(words), kept_cap=0, graph=False)
+                               nr + 8, 64 * len(words), kept_cap=0, graph=False,
+                               tune=L.make_tune(schedule=SCHEDULES[schedule]))
         runner.load(P.words_tensor(words)).run()
         torch.cuda.synchronize()
         out[mode] = (runner.sizes(), runner.error())
