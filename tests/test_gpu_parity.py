@@ -205,6 +205,63 @@ def test_giant_roads_span_many_tiles(bank, extreme):
     compare(ref, run_plain(words, f, q, cfg), PLAIN_KEYS, f"giant plain extreme={extreme}")
 
 
+def _boundary_stream(bank, rng, full, n_events, small):
+    """Events whose roads fill tiles exactly and then put roads without combinations (an empty
+    layer) where the next tile begins; with small roads (2^5 combinations each) the batch takes
+    the listed road-boundary path, with large ones (4^5) the inline path."""
+    n = 2 if small else 4
+    per_tile = 4096 // (n ** 5)
+    events = []
+    for e in range(n_events):
+        roads, tag = [], 1
+        # the first six events fill whole tiles; extra roads in the last three move the
+        # boundaries into roads
+        for r in range(per_tile + (e % 3 if e >= 6 else 0)):
+            hits = [(l, int(rng.integers(-4096, 4096))) for l in range(5) for _ in range(n)]
+            if full and r % 3 == 1:  # a noise-free track: the road has an accepted best
+                x = bank.A[tag] @ np.array([5, -6, 7]) + bank.b[tag]
+                for l in range(5):
+                    hits[n * l] = (l, int(x[l]))
+            roads.append((tag, [hits[i] for i in rng.permutation(len(hits))]))
+            tag += 1
+        for r in range(1 + e % 2):  # no combinations: layer 1 or 3 has no hit
+            empty = 1 if r == 0 else 3
+            hits = [(l, int(rng.integers(-4096, 4096))) for l in range(5) if l != empty
+                    for _ in range(1 + (l + r) % 2)]
+            roads.append((tag, hits))
+            tag += 1
+        if not full:  # every road of the batch without combinations
+            roads = roads[-(1 + e % 2):]
+        events.append(roads)
+    return stream(events)
+
+
+@pytest.mark.parametrize("small", [False, True])
+@pytest.mark.parametrize("full", [True, False])
+def test_roads_without_combinations_at_tile_boundaries(bank, small, full):
+    """Roads without combinations (an empty layer) exactly where tiles of 4096 and 8192
+    combinations begin, where the road holding a tile's first combination is not the tile's
+    first road; and (full=False) a batch with roads but no combination at all, so that the
+    fused kernel has no tile.  Every road's best track and count, with and without a kept
+    list."""
+    rng = np.random.default_rng(31 + 2 * small + full)
+    words = _boundary_stream(bank, rng, full, 9, small)
+    ref = oracle.run(words, bank.f, bank.q, CFG)
+    if full:
+        assert ref["n_combos"] > 2 * 8192
+        assert int(np.asarray(ref["best_k"]).max()) >= 0
+    else:
+        assert ref["n_combos"] == 0 and ref["n_roads"] > 0
+    for t in (L.make_tune(4096, 64, 256, 3, TILES), L.make_tune(8192, 32, 256, 2, TILES),
+              L.make_tune(4096, 16, 512, 1, TILES)):
+        for kept in (True, False):
+            got, _ = run_batch(words, bank.f, bank.q, CFG, ref=ref, tune=t, graph=False,
+                               kept=kept)
+            keys = BATCH_KEYS if kept else [k for k in BATCH_KEYS if "kept" not in k]
+            compare(ref, got, keys, f"boundary small={small} full={full} tile "
+                                    f"{t.tile_combos} kept={kept}")
+
+
 def test_empty_input(bank):
     words = np.zeros(0, np.uint32)
     got, _ = run_batch(words, bank.f, bank.q, CFG, ref=dict(n_roads=0, n_combos=0), graph=False)
