@@ -34,8 +34,9 @@ constexpr int kWordCap = 2048;         // coordinates staged per chunk (a road h
 constexpr int kTabCap = 2048;          // coordinate-pair table entries per chunk (<= 136/road)
 constexpr int kMapCap = kMaxTile / 4;  // groups of 4 combinations in a tile
 constexpr int kMaxLayerHits = SVT_MAX_HITS;  // hits on one layer of a road with combinations
-constexpr int64_t kListedMaxMean = 48;  // mean combinations per road below which road-spanning
-                                        // groups get a pass of their own (consume_listed)
+constexpr int kListedBit = 0x80;        // group map entry of a group listed in X (index below)
+constexpr int64_t kStashMinMean = 48;   // mean combinations per road from which the listed
+                                        // groups' records wait in LDS (consume_listed)
 
 struct FArgs {
     const svt_fconst *bank;
@@ -69,8 +70,11 @@ struct Stage {
     // chunk's last) and the table build's reads of kMaxLayerHits words from a layer's start
     alignas(16) int16_t G[kWordCap + 32];
     int32_t XT[kTabCap];                   // coordinate-pair tables
-    uint8_t M[kMapCap];                    // group of 4 combinations -> road of its first one
+    uint8_t M[kMapCap];                    // group of 4 combinations -> road of its first one,
+                                           // or kListedBit | its index in X
     uint16_t X[kChunk];                    // groups that span a road boundary (from g_lo)
+    uint8_t XR[kChunk];                    // road of the first combination of each group in X
+    uint8_t ready[kChunk];                 // group X[x]'s records are in the stash (see Stash)
     RoadMeta meta[kChunk];
     RoadConst rc[kChunk];
     int32_t rb[kChunk];                    // road begin relative to the tile start
@@ -302,7 +306,12 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
             const int32_t pg = __shfl_up(g, 1);
             const bool head = cut && !(pcut && pg == g);
             const uint64_t hm = __ballot(head);
-            if (head) S.X[__popcll(hm & ((1ull << lane) - 1))] = static_cast<uint16_t>(g - g_lo);
+            if (head) {
+                const int xi = __popcll(hm & ((1ull << lane) - 1));
+                S.X[xi] = static_cast<uint16_t>(g - g_lo);
+                S.XR[xi] = S.M[g - g_lo];  // written above by the road of the group's start
+                S.M[g - g_lo] = static_cast<uint8_t>(kListedBit | xi);
+            }
             if (lane == 0) S.nx = __popcll(hm);
         }
         if (lane == 0) {
@@ -318,6 +327,7 @@ __device__ void produce(const FArgs &a, Stage &S, Loader &L, int64_t n_roads, in
             S.work[0] = 0;
             S.work[1] = 0;
         }
+        S.ready[lane] = 0;  // kChunk lanes
         return;
     }
 }
@@ -332,15 +342,17 @@ __device__ __forceinline__ int32_t claim64(int32_t *counter) {
 }
 
 // A group whose valid slots all lie in staged road ri: four fits with one road's constants
-// (slots outside `slots` compute a harmless dummy, k = 0, and are not written).
-template <int MODE, int REC>
-__device__ __forceinline__ void fit_group(const FArgs &a, const Stage &S, int ri, int32_t rel0,
-                                          uint32_t slots, int64_t tile_start, int64_t r_first) {
+// (slots outside `slots` compute a harmless dummy, k = 0).  Returns the records and the accept
+// bits; the caller writes them.
+template <int MODE>
+__device__ __forceinline__ uint32_t fit_group(const FArgs &a, const Stage &S, int ri, int32_t rel0,
+                                              uint32_t slots, int64_t tile_start, int64_t r_first,
+                                              int32_t *vp0, int32_t *vp1, int32_t *vp2,
+                                              int32_t *vc0, int32_t *vc1, int32_t *vc2,
+                                              int64_t *vchi) {
     const RoadMeta m = S.meta[ri];
     const RoadConst c = S.rc[ri];
     const int32_t rbase = S.rb[ri];
-    int32_t vp0[4], vp1[4], vp2[4], vc0[4], vc1[4], vc2[4];
-    int64_t vchi[4];
     int32_t kk[4];
     Fit f4r[4];
     fit4<MODE>(m, c, rel0 - rbase, S.XT, a.shift, f4r);
@@ -372,35 +384,87 @@ __device__ __forceinline__ void fit_group(const FArgs &a, const Stage &S, int ri
         atomicMin(keys + r_first + ri, kmin);
         atomicAdd(a.best.n_accept + r_first + ri, __popc(acc_bits));
     }
-    store_group<REC>(a.rec, a.accept, gi, slots, acc_bits, vp0, vp1, vp2, vc0, vc1, vc2, vchi);
+    return acc_bits;
 }
 
-// One combination ci (relative to the tile start) of a group that spans a road boundary, fitted
-// with the constants of its own road (the group's first road is r; later roads follow in
-// staging order) and written on its own.  Such groups are few (at most one per road), but at
-// small roads one chunk can hold hundreds of them; one lane per combination rather than per
-// group spreads them over four times as many lanes.
+// The records of the groups that span a road boundary wait in LDS until the main pass writes
+// them with the same store instructions as their neighbours' records.  A 128-byte line whose
+// parts are written by different instructions at different times can reach memory in parts,
+// at a large cost (fitting those groups in a second round of the chunk instead raised the
+// written bytes by 16 % and the kernel time by 59 % on 3000 events of 2048 roads).  The stash
+// takes the staged coordinates' LDS, which no fit reads: per listed group its records
+// (REC > kRecNone), then 4 accept bytes per group.  A listed group past the capacity is written
+// by the listed pass itself.
+template <int REC>
+struct Stash {
+    static constexpr int kRecBytes = REC == kRecNone ? 0 : (REC == kRecFit ? 80 : 128);
+    static constexpr int kBytes = static_cast<int>(sizeof(Stage::G));
+    static constexpr int kCap = kBytes / (kRecBytes + 4) < kChunk ? kBytes / (kRecBytes + 4)
+                                                                  : kChunk;
+    // record layout: p0[4], p1[4], p2[4] (int32), chi2[4] (int64), then c0[4], c1[4], c2[4]
+    __device__ static int32_t *rec32(Stage &S, int x) {
+        return reinterpret_cast<int32_t *>(reinterpret_cast<uint8_t *>(S.G) + x * kRecBytes);
+    }
+    __device__ static int64_t *chi(Stage &S, int x) {
+        return reinterpret_cast<int64_t *>(reinterpret_cast<uint8_t *>(S.G) + x * kRecBytes + 48);
+    }
+    __device__ static uint8_t *acc(Stage &S, int x) {
+        return reinterpret_cast<uint8_t *>(S.G) + kCap * kRecBytes + 4 * x;
+    }
+};
+static_assert(Stash<kRecRows>::kCap >= 16 && Stash<kRecNone>::kCap == kChunk, "stash room");
+static_assert(kChunk <= kListedBit && kChunk == kWaveSize, "listed index; one loader lane per road");
+
+// A listed group's ready flag as an LDS address: a volatile access through a generic pointer
+// becomes a flat access, which also waits for every outstanding global store of the wave.
+typedef __attribute__((address_space(3))) volatile uint8_t lds_flag;
+__device__ __forceinline__ lds_flag *ready_flag(Stage &S, int x) {
+    return (lds_flag *)(&S.ready[x]);
+}
+
+// One combination ci (relative to the tile start) of listed group x (slot e), fitted with the
+// constants of its own road (the group's first road is r; later roads follow in staging order).
+// Its records go to the stash, or to memory past the stash's capacity.  Such groups are few (at
+// most one per road), but at small roads one chunk holds dozens of them; one lane per
+// combination rather than per group spreads them over four times as many lanes.
 template <int MODE, int REC>
-__device__ void fit_slot(const FArgs &a, const Stage &S, int r, int32_t ci, int64_t tile_start,
-                         int64_t r_first) {
+__device__ void fit_slot(const FArgs &a, Stage &S, int r, int32_t ci, int64_t tile_start,
+                         int64_t r_first, int x, int e, int xcap) {
     const int nr = S.nr;
     while (r + 1 < nr && ci >= S.rb[r] + S.meta[r].C()) ++r;  // skips empty roads
     const int32_t k = ci - S.rb[r];
     const Fit f = fit_combo<MODE>(S.meta[r], S.rc[r], static_cast<uint32_t>(k), S.XT, a.shift);
     const bool acc = f.chi2 <= a.cut;
     const int64_t gi = tile_start + ci;
-    if (REC != kRecNone) {
-        a.rec.p0[gi] = f.v[0];
-        a.rec.p1[gi] = f.v[1];
-        a.rec.p2[gi] = f.v[2];
-        a.rec.chi2[gi] = f.chi2;
+    if (x < xcap) {
+        if (REC != kRecNone) {
+            int32_t *q = Stash<REC>::rec32(S, x);
+            q[e] = f.v[0];
+            q[4 + e] = f.v[1];
+            q[8 + e] = f.v[2];
+            Stash<REC>::chi(S, x)[e] = f.chi2;
+        }
+        if (REC == kRecRows) {
+            int32_t *q = Stash<REC>::rec32(S, x);
+            q[20 + e] = f.v[3];
+            q[24 + e] = f.v[4];
+            q[28 + e] = f.v[5];
+        }
+        Stash<REC>::acc(S, x)[e] = acc ? 1 : 0;
+    } else {
+        if (REC != kRecNone) {
+            a.rec.p0[gi] = f.v[0];
+            a.rec.p1[gi] = f.v[1];
+            a.rec.p2[gi] = f.v[2];
+            a.rec.chi2[gi] = f.chi2;
+        }
+        if (REC == kRecRows) {
+            if (a.rec.c0) a.rec.c0[gi] = f.v[3];
+            if (a.rec.c1) a.rec.c1[gi] = f.v[4];
+            if (a.rec.c2) a.rec.c2[gi] = f.v[5];
+        }
+        a.accept[gi] = acc ? 1 : 0;
     }
-    if (REC == kRecRows) {
-        if (a.rec.c0) a.rec.c0[gi] = f.v[3];
-        if (a.rec.c1) a.rec.c1[gi] = f.v[4];
-        if (a.rec.c2) a.rec.c2[gi] = f.v[5];
-    }
-    a.accept[gi] = acc ? 1 : 0;
     if (acc) {
         unsigned long long *keys = reinterpret_cast<unsigned long long *>(a.best.chi2);
         if (a.kb_counts) atomicAdd(a.kb_counts + gi / kKeptBlock, 1ull);
@@ -410,17 +474,20 @@ __device__ void fit_slot(const FArgs &a, const Stage &S, int r, int32_t ci, int6
     }
 }
 
-// Compute waves, for batches of small roads: fit every combination of a staged chunk that lies
-// inside its tile.  A lane takes a group of 4 consecutive combinations.  Groups inside one
-// road take the uniform path (one road's constants, full 16-byte stores); the few groups that
-// span a road boundary are listed by the loader and fitted first, one combination per lane
-// with its own road's constants, so that every combination is written by exactly one lane.
-// Fitting the listed groups first lets the main pass complete their cache lines while the
-// lines are still in L2 (the other order leaves 16-byte holes that are filled too late and
-// reach HBM twice: 1.37x the algorithmic writes against 1.18x on a batch of 3000 events of
-// 64 roads, about 32 combinations each, when it was measured).
-template <int MODE, int REC>
+// Compute waves: fit every combination of a staged chunk that lies inside its tile.  A lane
+// takes a group of 4 consecutive combinations.  The groups that span a road boundary are listed
+// by the loader and fitted first, one combination per lane with its own road's constants.  In
+// the main pass every other group takes the uniform path (one road's constants, 16-byte stores).
+// With STASH (roads of 48 combinations or more on average) the listed groups' records wait in
+// the stash and each main-pass lane writes its group's records, fitted or from the stash, with
+// one set of store instructions for the whole wave.  Without it (small roads, where a chunk
+// holds many listed groups and the main pass would wait on them) the listed pass writes them
+// itself, before the main pass, so that the main pass completes their lines while they are
+// still in L2 (the other order wrote 1.37x the algorithmic bytes against 1.18x on 3000 events of
+// 64 roads of about 32 combinations).
+template <int MODE, int REC, bool STASH>
 __device__ void consume_listed(const FArgs &a, Stage &S) {
+    constexpr int xcap = STASH ? Stash<REC>::kCap : 0;
     const int32_t cs = S.cs, ce = S.ce, g_lo = S.g_lo, g_hi = S.g_hi;
     const int64_t tile_start = S.tile_start, r_first = S.r_first;
     const int32_t ng = g_hi - g_lo;
@@ -431,9 +498,16 @@ __device__ void consume_listed(const FArgs &a, Stage &S) {
         if (base >= 4 * nx) break;
         const int32_t j = base + lane;
         if (j < 4 * nx) {
-            const int32_t off = S.X[j >> 2];
-            const int32_t ci = ((g_lo + off) << 2) + (j & 3);
-            if (ci >= cs && ci < ce) fit_slot<MODE, REC>(a, S, S.M[off], ci, tile_start, r_first);
+            // a claim holds whole groups (base is a multiple of 64), so the lanes of slots 0..3
+            // of group x make their stash writes in one instruction stream
+            const int x = j >> 2, e = j & 3;
+            const int32_t ci = ((g_lo + S.X[x]) << 2) + e;
+            if (ci >= cs && ci < ce)
+                fit_slot<MODE, REC>(a, S, S.XR[x], ci, tile_start, r_first, x, e, xcap);
+            if (x < xcap) {
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the stash writes landed
+                if (e == 0) *ready_flag(S, x) = 1;
+            }
         }
     }
     while (true) {
@@ -443,125 +517,55 @@ __device__ void consume_listed(const FArgs &a, Stage &S) {
         if (it < ng) {
             const int32_t g = g_lo + it;
             const int32_t rel0 = g << 2;
-            const int ri = S.M[it];
-            const int32_t end = S.rb[ri] + S.meta[ri].C();  // end of road ri
-            uint32_t valid = 0, in_ri = 0;
+            const int mv = S.M[it];
+            uint32_t valid = 0;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                valid |= (rel0 + e >= cs && rel0 + e < ce) ? (1u << e) : 0u;
-                in_ri |= (rel0 + e < end) ? (1u << e) : 0u;
-            }
-            // a group spanning a road boundary is a listed group, fitted below
-            if (!(valid & ~in_ri)) fit_group<MODE, REC>(a, S, ri, rel0, valid, tile_start, r_first);
-        }
-    }
-}
-
-// Compute waves, for batches of large roads: each lane fits its group of 4 consecutive
-// combinations itself, a group that spans a road boundary slot by slot.  Large roads make such
-// groups rare inside a lane's work, and keeping them in the same pass adds no extra round to
-// the chunk; small roads make them frequent, and consume_listed() is then faster.
-template <int MODE, int REC>
-__device__ void consume_inline(const FArgs &a, Stage &S) {
-    const int nr = S.nr;
-    const int32_t cs = S.cs, ce = S.ce, g_lo = S.g_lo, g_hi = S.g_hi;
-    const int64_t tile_start = S.tile_start, r_first = S.r_first;
-    unsigned long long *keys = reinterpret_cast<unsigned long long *>(a.best.chi2);
-    const int32_t ng = g_hi - g_lo;
-    while (true) {
-        const int32_t base = claim64(&S.work[0]);
-        if (base >= ng) break;
-        if (base + lane_id() >= ng) continue;
-        const int32_t g = g_lo + base + lane_id();
-        const int32_t rel0 = g << 2;
-        const int32_t first = rel0 > cs ? rel0 : cs;
-        const int32_t last = (rel0 + 3 < ce - 1) ? rel0 + 3 : ce - 1;
-        int ri = S.M[g - g_lo];
-        RoadMeta m = S.meta[ri];
-        const int32_t rbase = S.rb[ri];
-        uint32_t valid_bits = 0;
+            for (int e = 0; e < 4; ++e) valid |= (rel0 + e >= cs && rel0 + e < ce) ? (1u << e) : 0u;
+            int32_t vp0[4], vp1[4], vp2[4], vc0[4], vc1[4], vc2[4];
+            int64_t vchi[4];
+            uint32_t acc_bits = 0, slots = 0;
+            if (mv & kListedBit) {
+                const int x = mv & (kListedBit - 1);
+                if (x < xcap) {
+                    // its slots were claimed before any main-pass work, by waves that finish
+                    // them without waiting on anything
+                    while (*ready_flag(S, x) == 0) __builtin_amdgcn_s_sleep(1);
+                    asm volatile("" ::: "memory");
+                    if (REC != kRecNone) {
+                        const int32_t *q = Stash<REC>::rec32(S, x);
+                        const int64_t *qc = Stash<REC>::chi(S, x);
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-            valid_bits |= (rel0 + e >= cs && rel0 + e < ce) ? (1u << e) : 0u;
-        int32_t vp0[4], vp1[4], vp2[4], vc0[4], vc1[4], vc2[4];
-        int64_t vchi[4];
-        int32_t kk[4];
-        int rr4[4];
-        const bool one_road = last - rbase < m.C();
-        if (one_road) {
-            // every valid combination of the group is in road ri: four independent fits
-            // (invalid slots compute a dummy k = 0)
-            const RoadConst c = S.rc[ri];
-            Fit f4r[4];
-            fit4<MODE>(m, c, rel0 - rbase, S.XT, a.shift, f4r);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const Fit &f = f4r[e];
-                vp0[e] = f.v[0]; vp1[e] = f.v[1]; vp2[e] = f.v[2];
-                vc0[e] = f.v[3]; vc1[e] = f.v[4]; vc2[e] = f.v[5];
-                vchi[e] = f.chi2;
-                kk[e] = rel0 + e - rbase;
-                rr4[e] = ri;
-            }
-        } else {
-            int32_t k = first - rbase;
-            RoadConst c = S.rc[ri];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                vp0[e] = vp1[e] = vp2[e] = vc0[e] = vc1[e] = vc2[e] = 0;
-                vchi[e] = 0;
-                kk[e] = 0;
-                rr4[e] = ri;
-                if ((valid_bits >> e) & 1u) {
-                    if (k >= m.C()) {
-                        while (k >= m.C() && ri + 1 < nr) {  // bounded by the chunk
-                            k -= m.C();
-                            ++ri;
-                            m = S.meta[ri];
+                        for (int e = 0; e < 4; ++e) {
+                            vp0[e] = q[e];
+                            vp1[e] = q[4 + e];
+                            vp2[e] = q[8 + e];
+                            vchi[e] = qc[e];
                         }
-                        c = S.rc[ri];
                     }
-                    const Fit f = fit_combo<MODE>(m, c, static_cast<uint32_t>(k), S.XT, a.shift);
-                    vp0[e] = f.v[0]; vp1[e] = f.v[1]; vp2[e] = f.v[2];
-                    vc0[e] = f.v[3]; vc1[e] = f.v[4]; vc2[e] = f.v[5];
-                    vchi[e] = f.chi2;
-                    kk[e] = k;
-                    rr4[e] = ri;
-                    ++k;
+                    if (REC == kRecRows) {
+                        const int32_t *q = Stash<REC>::rec32(S, x);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            vc0[e] = q[20 + e];
+                            vc1[e] = q[24 + e];
+                            vc2[e] = q[28 + e];
+                        }
+                    }
+                    const uint32_t w =
+                        *reinterpret_cast<const uint32_t *>(Stash<REC>::acc(S, x));
+                    acc_bits = ((w & 1u) | ((w >> 7) & 2u) | ((w >> 14) & 4u) | ((w >> 21) & 8u)) &
+                               valid;
+                    slots = valid;
                 }
-            }
-        }
-        uint32_t acc_bits = 0;
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-            acc_bits |= ((valid_bits >> e) & 1u) && vchi[e] <= a.cut ? (1u << e) : 0u;
-        const int64_t gi = tile_start + rel0;
-        if (acc_bits) {  // rare: reduce inside the group, then one global atomic per road
-            if (a.kb_counts)
-                atomicAdd(a.kb_counts + gi / kKeptBlock,
-                          static_cast<unsigned long long>(__popc(acc_bits)));
-            if (one_road) {
-                unsigned long long kmin = ~0ull;
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if ((acc_bits >> e) & 1u) {
-                        const unsigned long long kv = best_key(vchi[e], static_cast<uint32_t>(kk[e]));
-                        kmin = kv < kmin ? kv : kmin;
-                    }
-                atomicMin(keys + r_first + ri, kmin);
-                atomicAdd(a.best.n_accept + r_first + ri, __popc(acc_bits));
             } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if ((acc_bits >> e) & 1u) {
-                        atomicMin(keys + r_first + rr4[e],
-                                  static_cast<unsigned long long>(
-                                      best_key(vchi[e], static_cast<uint32_t>(kk[e]))));
-                        atomicAdd(a.best.n_accept + r_first + rr4[e], 1);
-                    }
+                acc_bits = fit_group<MODE>(a, S, mv, rel0, valid, tile_start, r_first, vp0, vp1,
+                                           vp2, vc0, vc1, vc2, vchi);
+                slots = valid;
             }
+            if (slots)
+                store_group<REC>(a.rec, a.accept, tile_start + rel0, slots, acc_bits, vp0, vp1,
+                                 vp2, vc0, vc1, vc2, vchi);
         }
-        store_group<REC>(a.rec, a.accept, gi, valid_bits, acc_bits, vp0, vp1, vp2, vc0, vc1, vc2, vchi);
     }
 }
 
@@ -604,8 +608,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG == 256 ? 
     if (n_tiles > a.tiles_cap) return;
     const int wave = threadIdx.x / kWaveSize;
     const uint32_t qlmask = (1u << a.shift) - 1u;
-    // road-boundary handling for this batch, from its mean combinations per road
-    const bool listed = n_combos < kListedMaxMean * n_roads;
+    // where the listed groups' records wait, from the batch's mean combinations per road
+    const bool stash = n_combos >= kStashMinMean * n_roads;
 
     Loader L;
     L.t = blockIdx.x;
@@ -643,14 +647,14 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG == 256 ? 
         // every wave, the loader once it has staged the next chunk
         constexpr int kWide = FOLD ? kFitFold : kFitSplit;
         if (S[cur].narrow) {
-            if (listed)
-                consume_listed<kFitNarrow, REC>(a, S[cur]);
+            if (stash)
+                consume_listed<kFitNarrow, REC, true>(a, S[cur]);
             else
-                consume_inline<kFitNarrow, REC>(a, S[cur]);
-        } else if (listed) {
-            consume_listed<kWide, REC>(a, S[cur]);
+                consume_listed<kFitNarrow, REC, false>(a, S[cur]);
+        } else if (stash) {
+            consume_listed<kWide, REC, true>(a, S[cur]);
         } else {
-            consume_inline<kWide, REC>(a, S[cur]);
+            consume_listed<kWide, REC, false>(a, S[cur]);
         }
         __syncthreads();
         cur ^= 1;
