@@ -510,6 +510,32 @@ __device__ void consume_listed(const FArgs &a, Stage &S) {
             }
         }
     }
+    if constexpr (!STASH) {
+        // the listed groups are written; the main pass fits and writes every other group
+        while (true) {
+            const int32_t base = claim64(&S.work[0]);
+            if (base >= ng) break;
+            const int32_t it = base + lane;
+            if (it < ng) {
+                const int mv = S.M[it];
+                if (!(mv & kListedBit)) {
+                    const int32_t rel0 = (g_lo + it) << 2;
+                    uint32_t valid = 0;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        valid |= (rel0 + e >= cs && rel0 + e < ce) ? (1u << e) : 0u;
+                    int32_t vp0[4], vp1[4], vp2[4], vc0[4], vc1[4], vc2[4];
+                    int64_t vchi[4];
+                    const uint32_t acc_bits = fit_group<MODE>(a, S, mv, rel0, valid, tile_start,
+                                                              r_first, vp0, vp1, vp2, vc0, vc1,
+                                                              vc2, vchi);
+                    store_group<REC>(a.rec, a.accept, tile_start + rel0, valid, acc_bits, vp0,
+                                     vp1, vp2, vc0, vc1, vc2, vchi);
+                }
+            }
+        }
+        return;
+    }
     while (true) {
         const int32_t base = claim64(&S.work[0]);
         if (base >= ng) break;
