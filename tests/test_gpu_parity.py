@@ -207,8 +207,9 @@ def test_giant_roads_span_many_tiles(bank, extreme):
 
 def _boundary_stream(bank, rng, full, n_events, small):
     """Events whose roads fill tiles exactly and then put roads without combinations (an empty
-    layer) where the next tile begins; with small roads (2^5 combinations each) the batch takes
-    the listed road-boundary path, with large ones (4^5) the inline path."""
+    layer) where the next tile begins; with small roads (2^5 combinations each) the batch's
+    road-spanning groups are written by the listed pass, with large ones (4^5) they go through
+    the LDS stash."""
     n = 2 if small else 4
     per_tile = 4096 // (n ** 5)
     events = []
